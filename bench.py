@@ -1,0 +1,213 @@
+"""Benchmark: SSP-RK3 steps of the unstructured-mesh finite-difference Euler
+residual on one MI355X.
+
+Workload: rotated Sod data (interface through (1/2, 1/2) at 30 degrees) on
+[0,1]^2, a jittered 1025 x 1025 triangulation (1,050,625 real vertices, random
+diagonals, +-0.15 h interior jitter, seed 0) with a 4-deep mirror ghost layer
+(reflecting walls y = 0, 1; extrapolating walls x = 0, 1), NU-WENO5 edge fluxes,
+degree-5 two-level least-squares divergence, SSP-RK3, FP64 (CFL: see SOD_CFL).
+
+One step = CFL reduction + 3 x (ghost fill, edge flux, vertex step + stage
+update), all in the HIP library, applied to the initial state (see SOD_CFL for
+why steps are not chained).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# The scheme's least-squares divergence of the Sod jump on jittered stencils
+# and at the mirrored walls drives the density negative after less than one
+# cell crossing of the waves, at any CFL number, so steps are not chained: every
+# timed step is one full SSP-RK3 step (CFL reduction + 3 stages) from the Sod
+# initial state into separate buffers.  The work per step does not depend on
+# the data; at this CFL one step from the initial state stays physical.
+SOD_CFL = 0.2
+METRIC = "vertex-stage updates/sec + HBM GB/s vs peak; batched & adjoint vs plain path"
+
+
+def kernel_bytes(A, precision_bytes=8):
+    """Algorithmic bytes per launch (each datum counted once).
+    edge:   per flux edge 6 int32 ids + 6 geometry values + 4 flux values written,
+            plus every state row read once;
+    vertex: per real vertex two CSR pointers, c_O (2), w_n (4) and the output (4),
+            per vertex entry an int32 id + 2 weights, per edge entry an int32 id +
+            1 weight, plus every state row and every flux row read once."""
+    s = precision_bytes
+    nvt, nvr, nef, nzv, nze = A["nv_total"], A["nv_real"], A["ne_flux"], A["nnz_v"], A["nnz_e"]
+    edge = nef * (6 * 4 + 6 * s + 4 * 8) + nvt * 4 * s
+    vertex = nvr * (2 * 4 + 2 * 8 + 4 * s + 4 * s) + nzv * (4 + 2 * s) + nze * (4 + s) + nvt * 4 * s + nef * 4 * 8
+    return dict(edge=edge, vertex=vertex)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "runtime.hip"):
+        with open(os.path.join(ROOT, "paper_2102_12933_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, N):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != source_hash() or d.get("N") != N:
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(mesh, w_input, budget_s=15.0, patch=48):
+    """Oracle stage timing on a bounded sample: a patch x patch block of real
+    vertices around the domain centre (the oracle computes their residual, i.e.
+    the fluxes of every edge their stencils use, and the stage update)."""
+    import numpy as np
+    import torch
+    from oracle.solver import Oracle
+
+    N = mesh.N
+    c = N // 2
+    ii, jj = np.meshgrid(np.arange(c - patch // 2, c + patch // 2), np.arange(c - patch // 2, c + patch // 2),
+                         indexing="ij")
+    sample = (ii * N + jj).ravel()
+    o = Oracle(mesh, deg=5, vertices=sample)
+    w = torch.from_numpy(w_input)
+    wn = w[sample].clone()
+    o.residual(w)                               # warm-up
+    n, t0 = 0, time.perf_counter()
+    while True:
+        R = o.residual(w)
+        _ = 0.75 * wn + 0.25 * (w[sample] + 1e-4 * R)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s and n >= 2:
+            break
+    return dict(value=len(sample) * n / el, unit="vertex-stage/s", cores=torch.get_num_threads(), kind="oracle",
+                sample=f"{len(sample)} real vertices ({patch}x{patch} block at the domain centre) of the same "
+                       f"1025^2 workload, {n} residual+stage evaluations on the state after one GPU step, "
+                       f"{el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--N", type=int, default=1025)
+    ap.add_argument("--reorder", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=30)
+    ap.add_argument("--cfl", type=float, default=SOD_CFL)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2102_12933_amd import fdu
+    from paper_2102_12933_amd.inputs import make_mesh, sod_state
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    t = time.perf_counter()
+    mesh = make_mesh(args.N, L=1.0, periodic=False, jitter=0.15, seed=0, ghost_layers=4)
+    log(f"mesh {args.N}^2: {mesh.nv_real} real + {mesh.ng} ghost vertices, {time.perf_counter() - t:.1f} s")
+    t = time.perf_counter()
+    prep = fdu.Prep(mesh, deg=5, level=0, reorder=args.reorder)
+    A = prep.arrays()
+    log(f"prep: {A['ne_flux']} flux edges, {A['nnz_v'] / A['nv_real']:.2f}+{A['nnz_e'] / A['nv_real']:.2f} "
+        f"stencil entries per vertex, {time.perf_counter() - t:.1f} s")
+    solver = fdu.Solver(prep, device=0)
+    perm = A["perm"]
+    w0 = torch.from_numpy(np.ascontiguousarray(sod_state(mesh)[perm])).cuda()
+    w1, w2, w3 = (torch.empty_like(w0) for _ in range(3))
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def step():
+        solver.cfl_dt(w0, args.cfl, dt)
+        solver.rk_stage(0, w0, w0, w1, dt)
+        solver.rk_stage(1, w0, w1, w2, dt)
+        solver.rk_stage(2, w0, w2, w3, dt)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    wr = w3[:A["nv_real"]]
+    rho = wr[:, 0]
+    p = 0.4 * (wr[:, 3] - 0.5 * (wr[:, 1] ** 2 + wr[:, 2] ** 2) / rho)
+    state_ok = bool(torch.isfinite(wr).all()) and float(rho.min()) > 0 and float(p.min()) > 0
+    log(f"state after one step: rho [{float(rho.min()):.4f}, {float(rho.max()):.4f}], "
+        f"p [{float(p.min()):.4f}, {float(p.max()):.4f}], dt {float(dt.item()):.3e}")
+    if not state_ok:
+        raise RuntimeError("non-physical state after a step")
+    w = w0
+    log(f"timed {args.steps} steps: {el * 1e3:.2f} ms")
+
+    kt = solver.kernel_times(w, reps=args.kernel_reps)
+    nb = kernel_bytes(A)
+    kern = {}
+    for k in ("edge", "vertex"):
+        ms = kt[k]
+        kern[k] = dict(avg_ms=ms, bytes=nb[k], gbs=nb[k] / (ms * 1e-3) / 1e9)
+    dom = max(("edge", "vertex"), key=lambda k: kt[k])
+    names = dict(edge="k_edge_flux", vertex="k_vertex")
+    traffic = traffic_from_profiles(names[dom], args.N)
+    achieved = kern[dom]["gbs"]
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    kernel=names[dom], avg_ms=round(kt[dom], 5), algorithmic_bytes=nb[dom])
+    nv_real = A["nv_real"]
+    value = nv_real * 3 * args.steps / el
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "vertex-stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"rotated Sod, jittered {args.N}x{args.N} triangulation of [0,1]^2 with 4-deep mirror "
+                               f"ghosts, NU-WENO5 + degree-5 two-level LS, one SSP-RK3 step (CFL {args.cfl}) from "
+                               f"the initial state per timed step",
+                   "nv_real": int(nv_real), "ne_flux": int(A["ne_flux"]), "nnz_v": int(A["nnz_v"]),
+                   "nnz_e": int(A["nnz_e"]), "reorder": "rcm" if args.reorder else "natural"},
+        "roofline": roofline,
+        "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in d.items()}
+                    for k, d in kern.items()} | {"ghost_ms": round(kt["ghost"], 5), "cfl_ms": round(kt["cfl"], 5)},
+    }
+    if not args.no_cpu_baseline:
+        w_in = np.empty((mesh.nv, 4))
+        w_in[perm] = w3.cpu().numpy()
+        log("cpu baseline (oracle on a bounded sample) ...")
+        out["cpu_baseline"] = cpu_baseline(mesh, w_in)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

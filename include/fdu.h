@@ -1,0 +1,211 @@
+/*
+ * fdu.h: C ABI of the MI355X (gfx950) library for the per-Runge-Kutta-stage
+ * residual of the unstructured-mesh finite-difference Euler scheme of
+ * Zhen, Qu and Cai, "A Novel Finite Difference Method for Euler Equations in
+ * 2D Unstructured Meshes".
+ *
+ * The residual of one stage is dw/dt = -(df/dx + dg/dy) at every real vertex
+ * (2D Euler equations, Sec. 2.1: w = [rho, rho u, rho v, rho E],
+ * p = (gamma-1) rho e), computed in two steps (abstract; Sec. 2.2, 2.3):
+ *   edge step   for every edge a divergence stencil uses, non-uniform WENO5
+ *               interpolation of characteristic variables at the edge midpoint
+ *               along the edge's six-point curvilinear stencil (Sec. 2.3.1,
+ *               Appendix), then the numerical flux projected on the edge
+ *               direction, r_k;
+ *   vertex step the least-squares divergence at vertex O as a weighted sum over
+ *               the stencil's vertex fluxes and edge projections (Sec. 2.2.1,
+ *               the weight row r_a1 + r_b2 of the pseudo-inverse), then the
+ *               SSP-RK3 stage update (the third-order TVD Runge-Kutta scheme of
+ *               Sec. 3).
+ *
+ * Conventions
+ *   - Every call returns fdu_status; on failure fdu_last_error() gives a
+ *     message (thread-local, valid until the next call on that thread).  No
+ *     C++ exception crosses this boundary.
+ *   - "host" pointers are read during the call only; the caller keeps
+ *     ownership.  "device" pointers are caller-owned device memory on the
+ *     solver's HIP device; the library never frees them.
+ *   - Compute calls are asynchronous on the given hipStream_t (passed as
+ *     void*; NULL = the default stream) and allocate nothing.  Set-up calls
+ *     (create, prep, upload, finalize) are synchronous.
+ *   - State layout: array of structures, vertex-major [nv_total][4] of
+ *     double (FDU_F64) or float (FDU_F32 storage); real vertices occupy rows
+ *     [0, nv_real), ghost vertices rows [nv_real, nv_total).  Residual and
+ *     cotangent arrays are [nv_real][4] (residual) or [nv_total][4] (state
+ *     cotangents).  Edge fluxes are [ne_flux][4] double.
+ *   - Vertex and edge numbering inside the library is the prep's order
+ *     (reverse Cuthill-McKee of the real vertices when requested); the prep
+ *     exposes the permutation so callers can map their arrays.
+ */
+#ifndef FDU_H
+#define FDU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FDU_OK = 0,
+  FDU_ERR_INVALID_ARG = 1, /* bad size, pointer, index or value */
+  FDU_ERR_HIP = 2,         /* a HIP runtime call failed */
+  FDU_ERR_OOM = 3,         /* device or host allocation failed */
+  FDU_ERR_STATE = 4,       /* call out of order (e.g. compute before finalize) */
+  FDU_ERR_UNSUPPORTED = 5, /* option not built */
+  FDU_ERR_NUMERIC = 6      /* rank-deficient least-squares system, bad stencil */
+} fdu_status;
+
+typedef enum { FDU_F64 = 0, FDU_F32 = 1 } fdu_precision;
+
+/* Scheme parameters.  Defaults (fdu_default_params): gamma 1.4 (Sec. 2.1),
+ * WENO eps 1e-40 and power 1 (Appendix), Roe flux with Harten's entropy fix
+ * delta = 0.1 * c_roe, positivity fallback on.
+ * positivity (not in the paper): when an interpolated midpoint state has
+ * rho <= 0 or p <= 0, that side of the edge uses its end vertex state. */
+typedef struct {
+  double gamma;
+  double weno_eps;
+  double entropy_frac;
+  int weno_power; /* 1 or 2 */
+  int riemann;    /* 0 = Roe + Harten fix, 1 = Rusanov */
+  int positivity; /* 0 or 1 */
+} fdu_params;
+
+const char* fdu_last_error(void);
+void fdu_default_params(fdu_params* out);
+
+/* ------------------------------------------------------------------------
+ * Host preprocessing (once per static mesh, Sec. 2.2.1: the weights depend on
+ * geometry only).  Builds, in C++ on the host:
+ *   - the divergence stencil of every real vertex (one-level: neighbours and
+ *     the edges of the incident triangles; two-level: the union of the
+ *     one-level stencils of the vertex and its neighbours, Sec. 2.2.2; a
+ *     one-level stencil with fewer than deg(deg+3)+4 conditions is promoted
+ *     to two-level);
+ *   - the least-squares weights by Householder QR with column pivoting of the
+ *     scaled system (the row r_a1 + r_b2 of the pseudo-inverse A^+, divided by
+ *     the scale h_O; pivots below 1e-10 of the first count as dependent, as in
+ *     a pseudo-inverse that drops zero singular values, and FDU_ERR_NUMERIC is
+ *     returned if the divergence is then not determined by the stencil);
+ *   - the six-point stencil (L3 L2 L1 R1 R2 R3) of every edge those stencils
+ *     use (L1 = smaller input id; each continuation is the neighbour that best
+ *     continues the previous segment's direction, cosines within 1e-12 tie to
+ *     the smaller input id) and its Catmull-Rom arc-length coordinates
+ *     (Sec. 2.3.1), normalised by the edge length;
+ *   - the vertex order (natural, or reverse Cuthill-McKee of the real
+ *     vertices) and the flux-edge order (by smallest new end id).
+ * Inputs (host, read only during the call):
+ *   xy [nv_total][2] double; edges [ne][2] int32 (a < b); tris [nt][3] int32;
+ *   ghost_src [ng] int32 (source real vertex of ghost nv_real+i),
+ *   ghost_refl [ng] int8 (bit 0: negate m_x, bit 1: negate m_y); ng =
+ *   nv_total - nv_real; periodic != 0 wraps displacements to the nearest image
+ *   in the box Lx x Ly.  deg = polynomial degree (3..6), level = 0 (automatic:
+ *   one-level for deg <= 3, two-level otherwise), 1 or 2; reorder = 0 natural,
+ *   1 reverse Cuthill-McKee.  nthreads <= 0 uses all host cores.
+ * Errors: FDU_ERR_INVALID_ARG for inconsistent sizes or ids, FDU_ERR_NUMERIC
+ * when an edge has no admissible stencil continuation or a least-squares
+ * matrix is rank deficient.
+ */
+typedef struct fdu_prep fdu_prep;
+
+typedef struct {
+  int64_t nv_total, nv_real, ne_flux, nnz_v, nnz_e;
+  /* arrays owned by the prep object, valid until fdu_prep_destroy */
+  const int32_t* perm;       /* [nv_total] new id -> input id */
+  const int32_t* iperm;      /* [nv_total] input id -> new id */
+  const int32_t* flux_edge;  /* [ne_flux] input edge id of each flux edge */
+  const int32_t* sten6;      /* [ne_flux][6] new vertex ids L3 L2 L1 R1 R2 R3 */
+  const double* geo;         /* [ne_flux][6] s0/d, s1/d, s4/d, s5/d, n_x, n_y */
+  const int32_t* vptr;       /* [nv_real+1] */
+  const int32_t* vcol;       /* [nnz_v] new vertex ids */
+  const double* wfg;         /* [nnz_v][2] (wf, wg) */
+  const int32_t* eptr;       /* [nv_real+1] */
+  const int32_t* ecol;       /* [nnz_e] flux-edge ids */
+  const double* we;          /* [nnz_e] */
+  const double* hmin;        /* [nv_real] shortest incident edge */
+  const int32_t* ghost_src;  /* [ng] new ids of the ghost sources */
+  const int8_t* ghost_refl;  /* [ng] */
+} fdu_prep_view;
+
+fdu_status fdu_prep_build(fdu_prep** out, int64_t nv_total, int64_t nv_real, const double* xy,
+                          int64_t ne, const int32_t* edges, int64_t nt, const int32_t* tris,
+                          const int32_t* ghost_src, const int8_t* ghost_refl, int periodic,
+                          double Lx, double Ly, int deg, int level, int reorder, int nthreads);
+fdu_status fdu_prep_view_get(const fdu_prep* prep, fdu_prep_view* out);
+void fdu_prep_destroy(fdu_prep* prep);
+
+/* ------------------------------------------------------------------------
+ * Solver: device-resident stencils and weights of one mesh instance.
+ * fdu_create selects hip_device and allocates nothing large.
+ * fdu_upload_* copy host arrays (layouts as in fdu_prep_view, all in the
+ * library's numbering) into library-owned device memory; they validate ids
+ * and CSR monotonicity and reject non-finite weights (FDU_ERR_INVALID_ARG).
+ * fdu_upload_prep uploads everything a prep built.  fdu_finalize derives
+ * the per-vertex sums c_O = sum_k we_k n_k and must precede compute calls.
+ */
+typedef struct fdu_solver fdu_solver;
+
+fdu_status fdu_create(fdu_solver** out, int hip_device, fdu_precision prec, const fdu_params* params);
+void fdu_destroy(fdu_solver* s);
+fdu_status fdu_upload_edge_stencils(fdu_solver* s, int64_t nv_total, int64_t nv_real, int64_t ne_flux,
+                                    const int32_t* sten6, const double* geo);
+fdu_status fdu_upload_vertex_stencils(fdu_solver* s, const int32_t* vptr, const int32_t* vcol,
+                                      const double* wfg, const int32_t* eptr, const int32_t* ecol,
+                                      const double* we, const double* hmin);
+fdu_status fdu_upload_ghosts(fdu_solver* s, int64_t ng, const int32_t* ghost_src, const int8_t* ghost_refl);
+fdu_status fdu_upload_prep(fdu_solver* s, const fdu_prep* prep);
+fdu_status fdu_finalize(fdu_solver* s);
+
+/* Sizes of the uploaded problem. */
+fdu_status fdu_sizes(const fdu_solver* s, int64_t* nv_total, int64_t* nv_real, int64_t* ne_flux,
+                     int64_t* nnz_v, int64_t* nnz_e);
+
+/* ------------------------------------------------------------------------
+ * Compute calls (asynchronous on stream, no allocation).
+ *
+ * fdu_fill_ghosts: rows [nv_real, nv_total) of w (device, in/out) := their
+ *   mirror sources with the flagged momentum components negated.
+ * fdu_edge_fluxes: r (device [ne_flux][4] double) := numerical flux
+ *   projections along each flux edge from the state w (device, read; ghost
+ *   rows must be filled).
+ * fdu_residual: fills the ghost rows of w (device, in/out: only ghost rows are
+ *   written), computes the edge fluxes into the solver's flux buffer and
+ *   writes R (device [nv_real][4]) = dw/dt at the real vertices.
+ * fdu_cfl_dt: dt_dev (device, one double) := cfl * min over real vertices of
+ *   hmin_v / (|u_v| + c_v).
+ * fdu_rk_stage: stage k in {0,1,2} of SSP-RK3 on the real rows:
+ *   w_out = a_k w_n + b_k (w_prev + dt R(w_prev)), (a,b) = (0,1), (3/4,1/4),
+ *   (1/3,2/3); dt read from dt_dev (device).  w_prev's ghost rows are filled;
+ *   w_out must not alias w_prev (other vertices gather from it) but may alias
+ *   w_n (each vertex reads only its own row of w_n); w_n is unused at k = 0;
+ *   w_out's ghost rows are not written.
+ * fdu_rk_step: one full SSP-RK3 step in place on w (device [nv_total][4]),
+ *   using scratch (device, two states [2][nv_total][4]); if cfl > 0 the step
+ *   first sets *dt_dev from the CFL condition, otherwise it reads *dt_dev.
+ * Errors: FDU_ERR_STATE before fdu_finalize; FDU_ERR_INVALID_ARG for NULL
+ * pointers or k out of range; FDU_ERR_HIP if a launch fails.
+ */
+fdu_status fdu_fill_ghosts(fdu_solver* s, void* w, void* stream);
+fdu_status fdu_edge_fluxes(fdu_solver* s, const void* w, double* r, void* stream);
+fdu_status fdu_residual(fdu_solver* s, void* w, void* R, void* stream);
+fdu_status fdu_cfl_dt(fdu_solver* s, const void* w, double cfl, double* dt_dev, void* stream);
+fdu_status fdu_rk_stage(fdu_solver* s, int k, const void* w_n, void* w_prev, void* w_out,
+                        const double* dt_dev, void* stream);
+fdu_status fdu_rk_step(fdu_solver* s, void* w, void* scratch, double cfl, double* dt_dev, void* stream);
+
+/* fdu_kernel_times: measurement aid.  Launches each kernel of a stage reps
+ * times back to back on stream, bracketed by HIP events, and writes the mean
+ * duration in milliseconds to avg_ms[0..3] = ghost fill, edge flux, vertex
+ * step (RK stage form), CFL reduction.  w (device state, ghost rows filled) is
+ * read and its ghost rows rewritten with the same values; scratch (device,
+ * [nv_total+1][4], same dtype as w) receives the time step in its first 8
+ * bytes and the stage output from row 1 on.  Synchronous: returns after the last launch.
+ * The timed work equals the work of the corresponding compute calls. */
+fdu_status fdu_kernel_times(fdu_solver* s, void* w, void* scratch, int reps, double* avg_ms, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDU_H */

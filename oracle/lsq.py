@@ -27,6 +27,9 @@ import numpy as np
 from .geometry import min_image
 
 
+RANK_TOL = 1e-10
+
+
 def monomial_exponents(deg: int):
     """(i, j) exponent pairs of x^i y^j, degree 1..deg, in the paper's order."""
     out = []
@@ -137,7 +140,8 @@ def ls_weights(mesh, topo: Topology, vertices, deg: int, level=None):
     vptr, vcol, wf, wg (vertex part) and eptr, ecol, we (edge part).
 
     The weight row is r_a1 + r_b2 of the SVD pseudo-inverse
-    A^+ = V diag(1/sigma) U^T, divided by h_O."""
+    A^+ = V diag(1/sigma) U^T (zero for sigma < RANK_TOL sigma_max), divided
+    by h_O."""
     exps = monomial_exponents(deg)
     M = len(exps)
     vertices = np.asarray(vertices, dtype=np.int64)
@@ -156,11 +160,19 @@ def ls_weights(mesh, topo: Topology, vertices, deg: int, level=None):
         E = np.stack([sten[i][1] for i in idx])
         A = _assemble(mesh, vertices[idx], V, E, exps, hO[idx])
         U, S, Vt = np.linalg.svd(A, full_matrices=False)
-        if np.any(S[:, -1] < 1e-12 * S[:, 0]):
-            bad = vertices[idx][S[:, -1] < 1e-12 * S[:, 0]]
-            raise ValueError(f"least-squares matrix of vertex {int(bad[0])} is rank deficient")
-        coef = (Vt[:, :, 0] + Vt[:, :, M + 1]) / S                       # [g, n]
-        rho = np.einsum("gk,gmk->gm", coef, U) / hO[idx][:, None]        # [g, m]
+        # pseudo-inverse: singular values below RANK_TOL * sigma_max count as zero
+        # (exactly symmetric stencils, e.g. mirror-ghost corners, are rank deficient)
+        Sinv = np.where(S > RANK_TOL * S[:, :1], 1.0 / S, 0.0)
+        coef = (Vt[:, :, 0] + Vt[:, :, M + 1]) * Sinv                    # [g, n]
+        rho = np.einsum("gk,gmk->gm", coef, U)                           # [g, m]
+        # the divergence must still be determined: A^T rho = e_a1 + e_b2
+        e = np.zeros(2 * M)
+        e[0] = e[M + 1] = 1.0
+        resid = np.abs(np.einsum("gmn,gm->gn", A, rho) - e).max(1)
+        if np.any(resid > 1e-8):
+            bad = vertices[idx][resid > 1e-8]
+            raise ValueError(f"divergence not determined by the stencil of vertex {int(bad[0])}")
+        rho = rho / hO[idx][:, None]
         for t, i in enumerate(idx):
             wv[i] = rho[t, :2 * a]
             wev[i] = rho[t, 2 * a:]

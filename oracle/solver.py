@@ -13,6 +13,10 @@ Per residual evaluation, in the paper's order (abstract; Sec. 2.2, 2.3):
      Sec. 2.2.1 times the weight row), and the residual dw/dt = -div.
 SSP-RK3 of Shu and Osher (the third-order TVD Runge-Kutta scheme Sec. 3 cites):
   w1 = w + dt R(w);  w2 = 3/4 w + 1/4 (w1 + dt R(w1));  w' = 1/3 w + 2/3 (w2 + dt R(w2)).
+Addition (not in the paper; ``positivity=False`` turns it off): where an
+interpolated midpoint state has rho <= 0 or p <= 0 (the WENO quadratics can
+overshoot on stencils that cross a discontinuity twice), that side of the edge
+falls back to its end vertex state (w_L = w_L1, w_R = w_R1).
 Readings: dt = CFL * min_v h_v / (|u_v| + c_v) over real vertices, h_v the
 shortest edge at v (the paper names the CFL number but no formula).  Walls (not
 in the paper, which has periodic and Dirichlet boundaries only): ghost states
@@ -33,8 +37,9 @@ from .nuweno import NUWeno5, WENO_EPS, WENO_POWER
 class Oracle:
     def __init__(self, mesh, deg: int = 5, level=None, vertices=None, gamma: float = euler.GAMMA,
                  weno_eps: float = WENO_EPS, weno_power: int = WENO_POWER,
-                 entropy_frac: float = 0.1, riemann: str = "roe"):
+                 entropy_frac: float = 0.1, riemann: str = "roe", positivity: bool = True):
         self.mesh = mesh
+        self.positivity = positivity
         self.gamma = gamma
         self.entropy_frac = entropy_frac
         self.riemann = riemann
@@ -87,7 +92,14 @@ class Oracle:
         cR = self.wenoR(C6[:, [5, 4, 3, 2, 1]])
         wL = torch.einsum("eij,ej->ei", R, cL)
         wR = torch.einsum("eij,ej->ei", R, cR)
+        if self.positivity:
+            wL = torch.where(self._physical(wL)[:, None], wL, W6[:, 2])
+            wR = torch.where(self._physical(wR)[:, None], wR, W6[:, 3])
         return wL, wR
+
+    def _physical(self, q):
+        rho, _, _, p = euler.primitives(q, self.gamma)
+        return (rho > 0) & (p > 0)
 
     def edge_fluxes(self, w: torch.Tensor) -> torch.Tensor:
         """Numerical flux projections r_k [ne_needed, 4] (edge order: self.edges)."""

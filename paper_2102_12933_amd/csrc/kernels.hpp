@@ -1,0 +1,390 @@
+// Device code of the per-stage residual: ghost fill, edge flux (non-uniform
+// WENO5 on characteristic variables + numerical flux), vertex least-squares
+// divergence with the fused SSP-RK3 stage update, CFL reduction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fdu {
+
+struct Scheme {
+  double gamma;   // ratio of specific heats
+  double gm1;     // gamma - 1
+  double eps;     // WENO epsilon
+  double efrac;   // Harten entropy-fix width as a fraction of the Roe sound speed
+  int power;      // WENO power (1 or 2)
+  int riemann;    // 0 Roe + Harten, 1 Rusanov
+  int positivity; // 1: a non-physical interpolated state falls back to its end vertex state
+};
+
+// ----------------------------------------------------------------------------
+// State access: array of structures [n][4]; one 32-byte (double) or 16-byte
+// (float) vector load per vertex.
+__device__ __forceinline__ void load4(const double* __restrict__ w, int v, double q[4]) {
+  const double2* p = reinterpret_cast<const double2*>(w + 4 * (size_t)v);
+  double2 a = p[0], b = p[1];
+  q[0] = a.x; q[1] = a.y; q[2] = b.x; q[3] = b.y;
+}
+__device__ __forceinline__ void load4(const float* __restrict__ w, int v, double q[4]) {
+  float4 a = reinterpret_cast<const float4*>(w)[v];
+  q[0] = a.x; q[1] = a.y; q[2] = a.z; q[3] = a.w;
+}
+__device__ __forceinline__ void store4(double* __restrict__ w, int v, const double q[4]) {
+  double2* p = reinterpret_cast<double2*>(w + 4 * (size_t)v);
+  p[0] = make_double2(q[0], q[1]);
+  p[1] = make_double2(q[2], q[3]);
+}
+__device__ __forceinline__ void store4(float* __restrict__ w, int v, const double q[4]) {
+  reinterpret_cast<float4*>(w)[v] = make_float4((float)q[0], (float)q[1], (float)q[2], (float)q[3]);
+}
+
+// Euler fluxes f, g of a conservative state (Sec. 2.1).
+__device__ __forceinline__ void euler_fg(const double q[4], double gm1, double f[4], double g[4]) {
+  const double ir = 1.0 / q[0];
+  const double u = q[1] * ir, v = q[2] * ir;
+  const double p = gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * v));
+  f[0] = q[1]; f[1] = q[1] * u + p; f[2] = q[1] * v; f[3] = (q[3] + p) * u;
+  g[0] = q[2]; g[1] = q[2] * u;     g[2] = q[2] * v + p; g[3] = (q[3] + p) * v;
+}
+
+// ----------------------------------------------------------------------------
+// Non-uniform WENO5 midpoint interpolation (Appendix).  Coordinates are
+// normalised by the middle-edge length, so x2 = -1/2 and x3 = +1/2 exactly and
+// the smoothness-indicator interval is [-1/2, 1/2] with dx = 1.
+struct WenoGeom {
+  double I[3][3];   // sub-stencil interpolation weights at 0 (Lagrange basis values)
+  double D1[3][3];  // first derivatives of the Lagrange basis at 0
+  double D2[3][3];  // second derivatives of the Lagrange basis
+  double C[3];      // optimal linear weights
+};
+
+// x0, x1, x4: the outer nodes (x2 = -1/2, x3 = 1/2).
+__device__ __forceinline__ void weno_geom(double x0, double x1, double x4, WenoGeom& G) {
+  const double x2 = -0.5, x3 = 0.5;
+  const double xs[5] = {x0, x1, x2, x3, x4};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double a = xs[k], b = xs[k + 1], c = xs[k + 2];
+    const double ia = 1.0 / ((a - b) * (a - c));
+    const double ib = 1.0 / ((b - a) * (b - c));
+    const double ic = 1.0 / ((c - a) * (c - b));
+    G.I[k][0] = b * c * ia;  G.I[k][1] = a * c * ib;  G.I[k][2] = a * b * ic;
+    G.D1[k][0] = -(b + c) * ia;  G.D1[k][1] = -(a + c) * ib;  G.D1[k][2] = -(a + b) * ic;
+    G.D2[k][0] = 2.0 * ia;  G.D2[k][1] = 2.0 * ib;  G.D2[k][2] = 2.0 * ic;
+  }
+  // linear weights: C0 and C2 from their closed forms, C1 = 1 - C0 - C2
+  const double i40 = 1.0 / (x4 - x0);
+  G.C[0] = x3 * x4 * i40 / (x3 - x0);
+  G.C[2] = x0 * x1 * i40 / (x4 - x1);
+  G.C[1] = 1.0 - G.C[0] - G.C[2];
+}
+
+// Nonlinear interpolant at 0 from values u[0..4] at the five nodes.
+__device__ __forceinline__ double weno_eval(const WenoGeom& G, const double u[5], double eps, int power) {
+  double ut[3], b[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double u0 = u[k], u1 = u[k + 1], u2 = u[k + 2];
+    ut[k] = G.I[k][0] * u0 + G.I[k][1] * u1 + G.I[k][2] * u2;
+    const double d1 = G.D1[k][0] * u0 + G.D1[k][1] * u1 + G.D1[k][2] * u2;
+    const double d2 = G.D2[k][0] * u0 + G.D2[k][1] * u1 + G.D2[k][2] * u2;
+    // beta = int_{-1/2}^{1/2} (q'^2 + q''^2) dx = q'(0)^2 + (13/12) q''^2
+    b[k] = d1 * d1 + (13.0 / 12.0) * d2 * d2 + eps;
+    if (power == 2) b[k] *= b[k];
+  }
+  // omega_k proportional to C_k / b_k: multiply through by b0 b1 b2
+  const double n0 = G.C[0] * b[1] * b[2];
+  const double n1 = G.C[1] * b[0] * b[2];
+  const double n2 = G.C[2] * b[0] * b[1];
+  return (n0 * ut[0] + n1 * ut[1] + n2 * ut[2]) / (n0 + n1 + n2);
+}
+
+// ----------------------------------------------------------------------------
+// Eigenvectors of A_n = n_x df/dw + n_y dg/dw at a Roe-averaged state:
+// columns (1, u - c n, H - c u_n), (1, u, q^2/2), (0, t, u_t), (1, u + c n, H + c u_n),
+// t = (-n_y, n_x); the left eigenvectors in closed form.
+struct Frame {
+  double u, v, H, c, un, ut, q2, nx, ny;
+};
+
+__device__ __forceinline__ Frame roe_frame(const double a[4], const double b[4], double nx, double ny, double gm1) {
+  Frame F;
+  const double ra = sqrt(a[0]), rb = sqrt(b[0]);
+  const double ia = 1.0 / a[0], ib = 1.0 / b[0];
+  const double ua = a[1] * ia, va = a[2] * ia, ub = b[1] * ib, vb = b[2] * ib;
+  const double pa = gm1 * (a[3] - 0.5 * (a[1] * ua + a[2] * va));
+  const double pb = gm1 * (b[3] - 0.5 * (b[1] * ub + b[2] * vb));
+  const double Ha = (a[3] + pa) * ia, Hb = (b[3] + pb) * ib;
+  const double is = 1.0 / (ra + rb);
+  F.u = (ra * ua + rb * ub) * is;
+  F.v = (ra * va + rb * vb) * is;
+  F.H = (ra * Ha + rb * Hb) * is;
+  F.q2 = 0.5 * (F.u * F.u + F.v * F.v);
+  F.c = sqrt(gm1 * (F.H - F.q2));
+  F.nx = nx;
+  F.ny = ny;
+  F.un = F.u * nx + F.v * ny;
+  F.ut = -F.u * ny + F.v * nx;
+  return F;
+}
+
+// characteristic variables l_k . q
+__device__ __forceinline__ void to_char(const Frame& F, double gm1, const double q[4], double o[4]) {
+  const double ic = 1.0 / F.c;
+  const double b1 = gm1 * ic * ic, b2 = b1 * F.q2;
+  const double mv = F.u * q[1] + F.v * q[2];            // u . m
+  const double nm = F.nx * q[1] + F.ny * q[2];          // n . m
+  const double tm = -F.ny * q[1] + F.nx * q[2];         // t . m
+  const double core = b2 * q[0] - b1 * mv + b1 * q[3];  // b2 rho - b1 u.m + b1 rhoE
+  o[0] = 0.5 * (core + (F.un * q[0] - nm) * ic);
+  o[1] = q[0] - core;
+  o[2] = tm - F.ut * q[0];
+  o[3] = 0.5 * (core - (F.un * q[0] - nm) * ic);
+}
+
+// conservative variables sum_k a_k r_k
+__device__ __forceinline__ void from_char(const Frame& F, const double a[4], double q[4]) {
+  const double s = a[0] + a[3], d = a[3] - a[0];
+  q[0] = s + a[1];
+  q[1] = F.u * (s + a[1]) + F.c * F.nx * d - F.ny * a[2];
+  q[2] = F.v * (s + a[1]) + F.c * F.ny * d + F.nx * a[2];
+  q[3] = F.H * s + F.c * F.un * d + F.q2 * a[1] + F.ut * a[2];
+}
+
+// rho > 0 and p > 0 (false for NaN as well)
+__device__ __forceinline__ bool physical(const double q[4], double gm1) {
+  if (!(q[0] > 0.0)) return false;
+  const double ir = 1.0 / q[0];
+  const double u = q[1] * ir, v = q[2] * ir;
+  const double p = gm1 * (q[3] - 0.5 * q[0] * (u * u + v * v));
+  return p > 0.0;
+}
+
+__device__ __forceinline__ double harten(double l, double delta) {
+  const double a = fabs(l);
+  return a < delta ? (l * l + delta * delta) / (2.0 * delta) : a;
+}
+
+__device__ __forceinline__ void normal_flux(const double q[4], double nx, double ny, double gm1, double F[4],
+                                            double* un_out = nullptr, double* c2_out = nullptr) {
+  const double ir = 1.0 / q[0];
+  const double u = q[1] * ir, v = q[2] * ir;
+  const double p = gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * v));
+  const double un = u * nx + v * ny;
+  F[0] = q[0] * un;
+  F[1] = q[1] * un + p * nx;
+  F[2] = q[2] * un + p * ny;
+  F[3] = (q[3] + p) * un;
+  if (un_out) *un_out = un;
+  if (c2_out) *c2_out = (gm1 + 1.0) * p * ir;
+}
+
+// Numerical flux along the edge direction n from the midpoint states wl, wr.
+__device__ __forceinline__ void riemann_flux(const double wl[4], const double wr[4], double nx, double ny,
+                                             const Scheme& S, double out[4]) {
+  double Fl[4], Fr[4], unl, unr, c2l, c2r;
+  normal_flux(wl, nx, ny, S.gm1, Fl, &unl, &c2l);
+  normal_flux(wr, nx, ny, S.gm1, Fr, &unr, &c2r);
+  if (S.riemann == 1) {
+    const double s = fmax(fabs(unl) + sqrt(c2l), fabs(unr) + sqrt(c2r));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = 0.5 * (Fl[k] + Fr[k]) - 0.5 * s * (wr[k] - wl[k]);
+    return;
+  }
+  const Frame F = roe_frame(wl, wr, nx, ny, S.gm1);
+  double dq[4], a[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) dq[k] = wr[k] - wl[k];
+  to_char(F, S.gm1, dq, a);
+  const double delta = S.efrac * F.c;
+  a[0] *= harten(F.un - F.c, delta);
+  a[1] *= harten(F.un, delta);
+  a[2] *= harten(F.un, delta);
+  a[3] *= harten(F.un + F.c, delta);
+  double d[4];
+  from_char(F, a, d);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[k] = 0.5 * (Fl[k] + Fr[k]) - 0.5 * d[k];
+}
+
+// Map a hardware block index to a logical one so that each of the 8 XCDs
+// (blocks are dealt to XCDs round robin) works on one contiguous range.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+// ----------------------------------------------------------------------------
+// Kernels.
+template <class T>
+__global__ void __launch_bounds__(256) k_fill_ghosts(T* __restrict__ w, int nreal, int ng, const int* __restrict__ src,
+                                                     const signed char* __restrict__ refl) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  double q[4];
+  load4(w, src[g], q);
+  const int f = refl[g];
+  if (f & 1) q[1] = -q[1];
+  if (f & 2) q[2] = -q[2];
+  store4(w, nreal + g, q);
+}
+
+template <class T, class TG>
+__global__ void __launch_bounds__(256) k_edge_flux(const T* __restrict__ w, const int* __restrict__ sten,
+                                                   const TG* __restrict__ geo, double* __restrict__ r, int ne,
+                                                   Scheme S) {
+  const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  int id[6];
+  {
+    const int2* sp = reinterpret_cast<const int2*>(sten + 6 * (size_t)e);
+    int2 a = sp[0], b = sp[1], c = sp[2];
+    id[0] = a.x; id[1] = a.y; id[2] = b.x; id[3] = b.y; id[4] = c.x; id[5] = c.y;
+  }
+  double W[6][4];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) load4(w, id[k], W[k]);
+  double g[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = (double)geo[6 * (size_t)e + k];
+  const double nx = g[4], ny = g[5];
+
+  // characteristic frame at the Roe average of the edge's end states
+  const Frame F = roe_frame(W[2], W[3], nx, ny, S.gm1);
+  double Cv[6][4];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) to_char(F, S.gm1, W[k], Cv[k]);
+
+  // left state from (L3 L2 L1 R1 R2); right state from the mirror (R3 R2 R1 L1 L2)
+  WenoGeom GL, GR;
+  weno_geom(g[0], g[1], g[2], GL);
+  weno_geom(-g[3], -g[2], -g[1], GR);
+  double cl[4], cr[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double ul[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
+    const double ur[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
+    cl[c] = weno_eval(GL, ul, S.eps, S.power);
+    cr[c] = weno_eval(GR, ur, S.eps, S.power);
+  }
+  double wl[4], wr[4];
+  from_char(F, cl, wl);
+  from_char(F, cr, wr);
+  if (S.positivity) {
+    if (!physical(wl, S.gm1))
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wl[k] = W[2][k];
+    if (!physical(wr, S.gm1))
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wr[k] = W[3][k];
+  }
+  double out[4];
+  riemann_flux(wl, wr, nx, ny, S, out);
+  double2* rp = reinterpret_cast<double2*>(r + 4 * (size_t)e);
+  rp[0] = make_double2(out[0], out[1]);
+  rp[1] = make_double2(out[2], out[3]);
+}
+
+// Vertex step.  LPV lanes cooperate on one vertex: each accumulates a strided
+// share of the vertex terms wf (f_j - f_O) + wg (g_j - g_O) and of the edge
+// terms we r_k; a butterfly over the LPV lanes reduces them, no atomics.
+// mode 0: R = -div.  mode 1: out = a w_n + b (w_prev + dt (-div)), w_prev = w.
+template <class T, class TW, int LPV>
+__global__ void __launch_bounds__(256) k_vertex(const T* __restrict__ w, const int* __restrict__ vptr,
+                                                const int* __restrict__ vcol, const TW* __restrict__ wfg,
+                                                const int* __restrict__ eptr, const int* __restrict__ ecol,
+                                                const TW* __restrict__ we, const double* __restrict__ cO,
+                                                const double* __restrict__ r, int nreal, double gm1, int mode,
+                                                T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
+                                                double a, double b, const double* __restrict__ dt_dev) {
+  const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int v = t / LPV, lane = t % LPV;
+  const bool active = v < nreal;
+  const int vv = active ? v : 0;
+  double q0[4], f0[4], g0[4];
+  load4(w, vv, q0);
+  euler_fg(q0, gm1, f0, g0);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (active) {
+    const int pe = vptr[v + 1];
+    for (int p = vptr[v] + lane; p < pe; p += LPV) {
+      const int j = vcol[p];
+      const double wf = (double)wfg[2 * (size_t)p], wg = (double)wfg[2 * (size_t)p + 1];
+      double q[4], f[4], g[4];
+      load4(w, j, q);
+      euler_fg(q, gm1, f, g);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] += wf * (f[k] - f0[k]) + wg * (g[k] - g0[k]);
+    }
+    const int qe = eptr[v + 1];
+    for (int p = eptr[v] + lane; p < qe; p += LPV) {
+      const int k = ecol[p];
+      const double c = (double)we[p];
+      const double2* rp = reinterpret_cast<const double2*>(r + 4 * (size_t)k);
+      const double2 x = rp[0], y = rp[1];
+      acc[0] += c * x.x; acc[1] += c * x.y; acc[2] += c * y.x; acc[3] += c * y.y;
+    }
+  }
+#pragma unroll
+  for (int m = LPV / 2; m >= 1; m >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += __shfl_xor(acc[k], m, LPV);
+  }
+  if (!active || lane != 0) return;
+  const double cx = cO[2 * (size_t)v], cy = cO[2 * (size_t)v + 1];
+  double res[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) res[k] = -(acc[k] - (cx * f0[k] + cy * g0[k]));
+  if (mode == 0) {
+    store4(R, v, res);
+  } else {
+    const double dt = *dt_dev;
+    double n[4] = {0.0, 0.0, 0.0, 0.0};
+    if (a != 0.0) load4(wn, v, n);
+    double o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = a * n[k] + b * (q0[k] + dt * res[k]);
+    store4(out, v, o);
+  }
+}
+
+// CFL time step: per-block minima of hmin_v / (|u_v| + c_v), then one block
+// reduces them and writes cfl * min.
+template <class T>
+__global__ void __launch_bounds__(256) k_cfl_partial(const T* __restrict__ w, const double* __restrict__ hmin, int nreal,
+                                                     double gamma, double* __restrict__ part) {
+  __shared__ double sm[256];
+  double best = 1e300;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nreal; v += gridDim.x * blockDim.x) {
+    double q[4];
+    load4(w, v, q);
+    const double ir = 1.0 / q[0];
+    const double u = q[1] * ir, vv = q[2] * ir;
+    const double p = (gamma - 1.0) * (q[3] - 0.5 * (q[1] * u + q[2] * vv));
+    const double s = sqrt(u * u + vv * vv) + sqrt(gamma * p * ir);
+    best = fmin(best, hmin[v] / s);
+  }
+  sm[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void __launch_bounds__(256) k_cfl_final(const double* __restrict__ part, int n, double cfl,
+                                                   double* __restrict__ dt) {
+  __shared__ double sm[256];
+  double best = 1e300;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) best = fmin(best, part[i]);
+  sm[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dt[0] = cfl * sm[0];
+}
+
+}  // namespace fdu

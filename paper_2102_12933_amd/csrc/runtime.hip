@@ -1,0 +1,496 @@
+// libfdu runtime: device buffers of one mesh instance, uploads with
+// validation, kernel launches and the C ABI of include/fdu.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fdu_internal.h"
+#include "kernels.hpp"
+
+namespace fdu {
+
+thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+#define FDU_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::fdu::Error(e_ == hipErrorOutOfMemory ? FDU_ERR_OOM : FDU_ERR_HIP,           \
+                         std::string(#call) + ": " + hipGetErrorString(e_));              \
+  } while (0)
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    FDU_HIP(hipMalloc(&p, count * sizeof(T)));
+    n = count;
+  }
+  void upload(const T* h, size_t count) {
+    alloc(count);
+    if (count) FDU_HIP(hipMemcpy(p, h, count * sizeof(T), hipMemcpyHostToDevice));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DevBuf() { release(); }
+};
+
+}  // namespace fdu
+
+using namespace fdu;
+
+struct fdu_solver {
+  int device = 0;
+  fdu_precision prec = FDU_F64;
+  fdu_params params{};
+  int64_t nv_total = 0, nv_real = 0, ne_flux = 0, nnz_v = 0, nnz_e = 0, ng = 0;
+  bool have_edges = false, have_vertices = false, finalized = false;
+  // host copies kept until finalize (c_O needs the edge directions and weights)
+  std::vector<double> h_geo, h_we;
+  std::vector<int32_t> h_eptr, h_ecol;
+  DevBuf<int32_t> sten, vptr, vcol, eptr, ecol, gsrc;
+  DevBuf<int8_t> grefl;
+  DevBuf<double> geo, wfg, we, cO, hmin, flux, part;
+  DevBuf<float> geo32, wfg32, we32;
+  int cfl_blocks = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int d) {
+    FDU_HIP(hipGetDevice(&prev));
+    if (prev != d) FDU_HIP(hipSetDevice(d));
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+void need(bool c, const char* msg) {
+  if (!c) throw Error(FDU_ERR_INVALID_ARG, msg);
+}
+
+void check_csr(const int32_t* ptr, int64_t n, const int32_t* col, int64_t ncol_max, const char* what, int64_t& nnz) {
+  need(ptr && col, "NULL CSR array");
+  need(ptr[0] == 0, "CSR pointer must start at 0");
+  for (int64_t i = 0; i < n; ++i)
+    if (ptr[i + 1] < ptr[i]) throw Error(FDU_ERR_INVALID_ARG, std::string(what) + ": CSR pointer not monotone");
+  nnz = ptr[n];
+  for (int64_t p = 0; p < nnz; ++p)
+    if (col[p] < 0 || col[p] >= ncol_max) throw Error(FDU_ERR_INVALID_ARG, std::string(what) + ": column id out of range");
+}
+
+void check_finite(const double* x, int64_t n, const char* what) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) throw Error(FDU_ERR_INVALID_ARG, std::string(what) + ": non-finite value");
+}
+
+Scheme scheme_of(const fdu_solver* s) {
+  Scheme S;
+  S.gamma = s->params.gamma;
+  S.gm1 = s->params.gamma - 1.0;
+  S.eps = s->params.weno_eps;
+  S.efrac = s->params.entropy_frac;
+  S.power = s->params.weno_power;
+  S.riemann = s->params.riemann;
+  S.positivity = s->params.positivity;
+  return S;
+}
+
+void ready(const fdu_solver* s) {
+  if (!s) throw Error(FDU_ERR_INVALID_ARG, "NULL solver");
+  if (!s->finalized) throw Error(FDU_ERR_STATE, "solver not finalized");
+}
+
+inline unsigned nblocks(int64_t nthreads) { return (unsigned)((nthreads + 255) / 256); }
+
+void launch_check() { FDU_HIP(hipGetLastError()); }
+
+template <class T>
+void fill_ghosts_t(fdu_solver* s, T* w, hipStream_t st) {
+  if (s->ng == 0) return;
+  hipLaunchKernelGGL(k_fill_ghosts<T>, dim3(nblocks(s->ng)), dim3(256), 0, st, w, (int)s->nv_real, (int)s->ng,
+                     s->gsrc.p, reinterpret_cast<const signed char*>(s->grefl.p));
+  launch_check();
+}
+
+template <class T>
+void edge_flux_t(fdu_solver* s, const T* w, double* r, hipStream_t st) {
+  if (s->ne_flux == 0) return;
+  const Scheme S = scheme_of(s);
+  if (s->prec == FDU_F64)
+    hipLaunchKernelGGL((k_edge_flux<T, double>), dim3(nblocks(s->ne_flux)), dim3(256), 0, st, w, s->sten.p, s->geo.p,
+                       r, (int)s->ne_flux, S);
+  else
+    hipLaunchKernelGGL((k_edge_flux<T, float>), dim3(nblocks(s->ne_flux)), dim3(256), 0, st, w, s->sten.p,
+                       s->geo32.p, r, (int)s->ne_flux, S);
+  launch_check();
+}
+
+constexpr int kLPV = 16;
+
+template <class T>
+void vertex_t(fdu_solver* s, const T* w, int mode, T* R, const T* wn, T* out, double a, double b, const double* dt,
+              hipStream_t st) {
+  const unsigned nb = nblocks(s->nv_real * kLPV);
+  const double gm1 = s->params.gamma - 1.0;
+  if (s->prec == FDU_F64)
+    hipLaunchKernelGGL((k_vertex<T, double, kLPV>), dim3(nb), dim3(256), 0, st, w, s->vptr.p, s->vcol.p, s->wfg.p,
+                       s->eptr.p, s->ecol.p, s->we.p, s->cO.p, s->flux.p, (int)s->nv_real, gm1, mode, R, wn, out, a,
+                       b, dt);
+  else
+    hipLaunchKernelGGL((k_vertex<T, float, kLPV>), dim3(nb), dim3(256), 0, st, w, s->vptr.p, s->vcol.p, s->wfg32.p,
+                       s->eptr.p, s->ecol.p, s->we32.p, s->cO.p, s->flux.p, (int)s->nv_real, gm1, mode, R, wn, out,
+                       a, b, dt);
+  launch_check();
+}
+
+template <class T>
+void cfl_t(fdu_solver* s, const T* w, double cfl, double* dt, hipStream_t st) {
+  hipLaunchKernelGGL(k_cfl_partial<T>, dim3(s->cfl_blocks), dim3(256), 0, st, w, s->hmin.p, (int)s->nv_real,
+                     s->params.gamma, s->part.p);
+  launch_check();
+  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, st, s->part.p, s->cfl_blocks, cfl, dt);
+  launch_check();
+}
+
+template <class T>
+void residual_t(fdu_solver* s, T* w, T* R, hipStream_t st) {
+  fill_ghosts_t<T>(s, w, st);
+  edge_flux_t<T>(s, w, s->flux.p, st);
+  vertex_t<T>(s, w, 0, R, nullptr, nullptr, 0.0, 0.0, nullptr, st);
+}
+
+const double kRK[3][2] = {{0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
+
+template <class T>
+void rk_stage_t(fdu_solver* s, int k, const T* wn, T* wprev, T* wout, const double* dt, hipStream_t st) {
+  fill_ghosts_t<T>(s, wprev, st);
+  edge_flux_t<T>(s, wprev, s->flux.p, st);
+  vertex_t<T>(s, wprev, 1, nullptr, wn, wout, kRK[k][0], kRK[k][1], dt, st);
+}
+
+template <class T>
+void rk_step_t(fdu_solver* s, T* w, T* scratch, double cfl, double* dt, hipStream_t st) {
+  T* w1 = scratch;
+  T* w2 = scratch + 4 * s->nv_total;
+  if (cfl > 0) cfl_t<T>(s, w, cfl, dt, st);
+  rk_stage_t<T>(s, 0, w, w, w1, dt, st);
+  rk_stage_t<T>(s, 1, w, w1, w2, dt, st);
+  rk_stage_t<T>(s, 2, w, w2, w, dt, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fdu_last_error(void) { return g_last_error.c_str(); }
+
+void fdu_default_params(fdu_params* p) {
+  if (!p) return;
+  p->gamma = 1.4;
+  p->weno_eps = 1e-40;
+  p->entropy_frac = 0.1;
+  p->weno_power = 1;
+  p->riemann = 0;
+  p->positivity = 1;
+}
+
+fdu_status fdu_create(fdu_solver** out, int hip_device, fdu_precision prec, const fdu_params* params) {
+  return guard([&] {
+    need(out != nullptr, "NULL output pointer");
+    *out = nullptr;
+    need(prec == FDU_F64 || prec == FDU_F32, "unknown precision");
+    int n = 0;
+    FDU_HIP(hipGetDeviceCount(&n));
+    need(hip_device >= 0 && hip_device < n, "no such HIP device");
+    auto s = new fdu_solver();
+    s->device = hip_device;
+    s->prec = prec;
+    if (params)
+      s->params = *params;
+    else
+      fdu_default_params(&s->params);
+    if (!(s->params.gamma > 1.0) || !(s->params.weno_eps > 0) || (s->params.weno_power != 1 && s->params.weno_power != 2) ||
+        (s->params.riemann != 0 && s->params.riemann != 1) || !(s->params.entropy_frac >= 0) ||
+        (s->params.positivity != 0 && s->params.positivity != 1)) {
+      delete s;
+      throw Error(FDU_ERR_INVALID_ARG, "invalid scheme parameters");
+    }
+    *out = s;
+  });
+}
+
+void fdu_destroy(fdu_solver* s) {
+  if (!s) return;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(s->device);
+  delete s;
+  (void)hipSetDevice(prev);
+}
+
+fdu_status fdu_upload_edge_stencils(fdu_solver* s, int64_t nv_total, int64_t nv_real, int64_t ne_flux,
+                                    const int32_t* sten6, const double* geo) {
+  return guard([&] {
+    need(s && sten6 && geo, "NULL argument");
+    need(nv_total > 0 && nv_real > 0 && nv_real <= nv_total && nv_total < INT32_MAX / 4, "invalid vertex counts");
+    need(ne_flux > 0 && ne_flux < INT32_MAX / 6, "invalid edge count");
+    for (int64_t i = 0; i < 6 * ne_flux; ++i)
+      need(sten6[i] >= 0 && sten6[i] < nv_total, "edge stencil vertex id out of range");
+    check_finite(geo, 6 * ne_flux, "edge geometry");
+    DeviceGuard dg(s->device);
+    s->finalized = false;
+    s->nv_total = nv_total;
+    s->nv_real = nv_real;
+    s->ne_flux = ne_flux;
+    s->ng = nv_total - nv_real;
+    s->sten.upload(sten6, 6 * ne_flux);
+    s->h_geo.assign(geo, geo + 6 * ne_flux);
+    if (s->prec == FDU_F64) {
+      s->geo.upload(geo, 6 * ne_flux);
+    } else {
+      std::vector<float> g32(geo, geo + 6 * ne_flux);
+      s->geo32.upload(g32.data(), g32.size());
+    }
+    s->flux.alloc(4 * ne_flux);
+    s->have_edges = true;
+  });
+}
+
+fdu_status fdu_upload_vertex_stencils(fdu_solver* s, const int32_t* vptr, const int32_t* vcol, const double* wfg,
+                                      const int32_t* eptr, const int32_t* ecol, const double* we, const double* hmin) {
+  return guard([&] {
+    need(s && wfg && we && hmin, "NULL argument");
+    if (!s->have_edges) throw Error(FDU_ERR_STATE, "upload the edge stencils first");
+    int64_t nnz_v, nnz_e;
+    check_csr(vptr, s->nv_real, vcol, s->nv_total, "vertex stencil", nnz_v);
+    check_csr(eptr, s->nv_real, ecol, s->ne_flux, "edge stencil", nnz_e);
+    check_finite(wfg, 2 * nnz_v, "vertex weights");
+    check_finite(we, nnz_e, "edge weights");
+    for (int64_t i = 0; i < s->nv_real; ++i) need(hmin[i] > 0 && std::isfinite(hmin[i]), "hmin must be positive");
+    DeviceGuard dg(s->device);
+    s->finalized = false;
+    s->nnz_v = nnz_v;
+    s->nnz_e = nnz_e;
+    s->vptr.upload(vptr, s->nv_real + 1);
+    s->vcol.upload(vcol, nnz_v);
+    s->eptr.upload(eptr, s->nv_real + 1);
+    s->ecol.upload(ecol, nnz_e);
+    s->hmin.upload(hmin, s->nv_real);
+    if (s->prec == FDU_F64) {
+      s->wfg.upload(wfg, 2 * nnz_v);
+      s->we.upload(we, nnz_e);
+    } else {
+      std::vector<float> a(wfg, wfg + 2 * nnz_v), b(we, we + nnz_e);
+      s->wfg32.upload(a.data(), a.size());
+      s->we32.upload(b.data(), b.size());
+    }
+    s->h_eptr.assign(eptr, eptr + s->nv_real + 1);
+    s->h_ecol.assign(ecol, ecol + nnz_e);
+    s->h_we.assign(we, we + nnz_e);
+    if (s->prec == FDU_F32)  // c_O must use the weights the kernels see
+      for (auto& x : s->h_we) x = (double)(float)x;
+    s->have_vertices = true;
+  });
+}
+
+fdu_status fdu_upload_ghosts(fdu_solver* s, int64_t ng, const int32_t* ghost_src, const int8_t* ghost_refl) {
+  return guard([&] {
+    need(s != nullptr, "NULL solver");
+    if (!s->have_edges) throw Error(FDU_ERR_STATE, "upload the edge stencils first");
+    need(ng == s->ng, "ghost count must equal nv_total - nv_real");
+    if (ng == 0) return;
+    need(ghost_src && ghost_refl, "NULL ghost arrays");
+    for (int64_t i = 0; i < ng; ++i) {
+      need(ghost_src[i] >= 0 && ghost_src[i] < s->nv_real, "ghost source must be a real vertex");
+      need((ghost_refl[i] & ~3) == 0, "ghost reflection flags must be in 0..3");
+    }
+    DeviceGuard dg(s->device);
+    s->finalized = false;
+    s->gsrc.upload(ghost_src, ng);
+    s->grefl.upload(ghost_refl, ng);
+  });
+}
+
+fdu_status fdu_upload_prep(fdu_solver* s, const fdu_prep* p) {
+  fdu_status st;
+  if (!s || !p) {
+    set_last_error("NULL argument");
+    return FDU_ERR_INVALID_ARG;
+  }
+  if ((st = fdu_upload_edge_stencils(s, p->nv_total, p->nv_real, p->ne_flux, p->sten6.data(), p->geo.data())) != FDU_OK)
+    return st;
+  if ((st = fdu_upload_vertex_stencils(s, p->vptr.data(), p->vcol.data(), p->wfg.data(), p->eptr.data(),
+                                       p->ecol.data(), p->we.data(), p->hmin.data())) != FDU_OK)
+    return st;
+  return fdu_upload_ghosts(s, p->nv_total - p->nv_real, p->ghost_src.data(), p->ghost_refl.data());
+}
+
+fdu_status fdu_finalize(fdu_solver* s) {
+  return guard([&] {
+    need(s != nullptr, "NULL solver");
+    if (!s->have_edges || !s->have_vertices) throw Error(FDU_ERR_STATE, "upload edge and vertex stencils first");
+    if (s->ng > 0 && s->gsrc.n != (size_t)s->ng) throw Error(FDU_ERR_STATE, "upload the ghosts first");
+    DeviceGuard dg(s->device);
+    std::vector<double> c(2 * s->nv_real, 0.0);
+    for (int64_t v = 0; v < s->nv_real; ++v)
+      for (int32_t p = s->h_eptr[v]; p < s->h_eptr[v + 1]; ++p) {
+        const int32_t k = s->h_ecol[p];
+        double nx = s->h_geo[6 * k + 4], ny = s->h_geo[6 * k + 5];
+        if (s->prec == FDU_F32) {
+          nx = (double)(float)nx;
+          ny = (double)(float)ny;
+        }
+        c[2 * v] += s->h_we[p] * nx;
+        c[2 * v + 1] += s->h_we[p] * ny;
+      }
+    s->cO.upload(c.data(), c.size());
+    s->cfl_blocks = (int)std::min<int64_t>(1024, (s->nv_real + 255) / 256);
+    s->part.alloc(s->cfl_blocks);
+    s->finalized = true;
+  });
+}
+
+fdu_status fdu_sizes(const fdu_solver* s, int64_t* nv_total, int64_t* nv_real, int64_t* ne_flux, int64_t* nnz_v,
+                     int64_t* nnz_e) {
+  return guard([&] {
+    need(s != nullptr, "NULL solver");
+    if (nv_total) *nv_total = s->nv_total;
+    if (nv_real) *nv_real = s->nv_real;
+    if (ne_flux) *ne_flux = s->ne_flux;
+    if (nnz_v) *nnz_v = s->nnz_v;
+    if (nnz_e) *nnz_e = s->nnz_e;
+  });
+}
+
+fdu_status fdu_fill_ghosts(fdu_solver* s, void* w, void* stream) {
+  return guard([&] {
+    ready(s);
+    need(w != nullptr, "NULL state");
+    DeviceGuard dg(s->device);
+    if (s->prec == FDU_F64)
+      fill_ghosts_t<double>(s, (double*)w, (hipStream_t)stream);
+    else
+      fill_ghosts_t<float>(s, (float*)w, (hipStream_t)stream);
+  });
+}
+
+fdu_status fdu_edge_fluxes(fdu_solver* s, const void* w, double* r, void* stream) {
+  return guard([&] {
+    ready(s);
+    need(w && r, "NULL argument");
+    DeviceGuard dg(s->device);
+    if (s->prec == FDU_F64)
+      edge_flux_t<double>(s, (const double*)w, r, (hipStream_t)stream);
+    else
+      edge_flux_t<float>(s, (const float*)w, r, (hipStream_t)stream);
+  });
+}
+
+fdu_status fdu_residual(fdu_solver* s, void* w, void* R, void* stream) {
+  return guard([&] {
+    ready(s);
+    need(w && R, "NULL argument");
+    DeviceGuard dg(s->device);
+    if (s->prec == FDU_F64)
+      residual_t<double>(s, (double*)w, (double*)R, (hipStream_t)stream);
+    else
+      residual_t<float>(s, (float*)w, (float*)R, (hipStream_t)stream);
+  });
+}
+
+fdu_status fdu_cfl_dt(fdu_solver* s, const void* w, double cfl, double* dt_dev, void* stream) {
+  return guard([&] {
+    ready(s);
+    need(w && dt_dev, "NULL argument");
+    need(cfl > 0 && std::isfinite(cfl), "cfl must be positive");
+    DeviceGuard dg(s->device);
+    if (s->prec == FDU_F64)
+      cfl_t<double>(s, (const double*)w, cfl, dt_dev, (hipStream_t)stream);
+    else
+      cfl_t<float>(s, (const float*)w, cfl, dt_dev, (hipStream_t)stream);
+  });
+}
+
+fdu_status fdu_rk_stage(fdu_solver* s, int k, const void* w_n, void* w_prev, void* w_out, const double* dt_dev,
+                        void* stream) {
+  return guard([&] {
+    ready(s);
+    need(k >= 0 && k <= 2, "stage must be 0, 1 or 2");
+    need(w_prev && w_out && dt_dev && (k == 0 || w_n), "NULL argument");
+    need(w_out != w_prev, "w_out must not alias w_prev (other vertices gather from it)");
+    DeviceGuard dg(s->device);
+    if (s->prec == FDU_F64)
+      rk_stage_t<double>(s, k, (const double*)w_n, (double*)w_prev, (double*)w_out, dt_dev, (hipStream_t)stream);
+    else
+      rk_stage_t<float>(s, k, (const float*)w_n, (float*)w_prev, (float*)w_out, dt_dev, (hipStream_t)stream);
+  });
+}
+
+fdu_status fdu_rk_step(fdu_solver* s, void* w, void* scratch, double cfl, double* dt_dev, void* stream) {
+  return guard([&] {
+    ready(s);
+    need(w && scratch && dt_dev, "NULL argument");
+    DeviceGuard dg(s->device);
+    if (s->prec == FDU_F64)
+      rk_step_t<double>(s, (double*)w, (double*)scratch, cfl, dt_dev, (hipStream_t)stream);
+    else
+      rk_step_t<float>(s, (float*)w, (float*)scratch, cfl, dt_dev, (hipStream_t)stream);
+  });
+}
+
+fdu_status fdu_kernel_times(fdu_solver* s, void* w, void* scratch, int reps, double* avg_ms, void* stream) {
+  return guard([&] {
+    ready(s);
+    need(w && scratch && avg_ms && reps > 0, "invalid argument");
+    DeviceGuard dg(s->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    FDU_HIP(hipEventCreate(&e0));
+    FDU_HIP(hipEventCreate(&e1));
+    auto timed = [&](auto&& launch) {
+      launch();  // warm
+      FDU_HIP(hipEventRecord(e0, st));
+      for (int i = 0; i < reps; ++i) launch();
+      FDU_HIP(hipEventRecord(e1, st));
+      FDU_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      FDU_HIP(hipEventElapsedTime(&ms, e0, e1));
+      return (double)ms / reps;
+    };
+    double* dt = reinterpret_cast<double*>(scratch);  // the first 8 bytes of scratch hold dt, rows 1.. the output
+    if (s->prec == FDU_F64) {
+      double* W = (double*)w;
+      double* out = (double*)scratch;
+      avg_ms[0] = timed([&] { fill_ghosts_t<double>(s, W, st); });
+      avg_ms[3] = timed([&] { cfl_t<double>(s, W, 0.5, dt, st); });
+      avg_ms[1] = timed([&] { edge_flux_t<double>(s, W, s->flux.p, st); });
+      avg_ms[2] = timed([&] { vertex_t<double>(s, W, 1, nullptr, W, out + 4, 0.75, 0.25, dt, st); });
+    } else {
+      float* W = (float*)w;
+      float* out = (float*)scratch;
+      avg_ms[0] = timed([&] { fill_ghosts_t<float>(s, W, st); });
+      avg_ms[3] = timed([&] { cfl_t<float>(s, W, 0.5, dt, st); });
+      avg_ms[1] = timed([&] { edge_flux_t<float>(s, W, s->flux.p, st); });
+      avg_ms[2] = timed([&] { vertex_t<float>(s, W, 1, nullptr, W, out + 4, 0.75, 0.25, dt, st); });
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+"""CPU tests of the C ABI library: every declared symbol is exported, the host
+preprocessing agrees with the oracle's (identical stencil index sets, arc
+coordinates and least-squares weights to rounding), and set-up errors are
+reported as status codes.  No compute call (those need the GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.solver import Oracle
+from paper_2102_12933_amd import fdu
+from paper_2102_12933_amd.inputs import make_mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "fdu.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdu_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = ctypes.CDLL(fdu.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(fdu.exported_symbols())
+
+
+CASES = [(33, True, 0, 3, 1), (33, True, 0, 5, 1), (18, False, 4, 5, 0), (18, False, 4, 5, 1),
+         (65, False, 4, 5, 1)]   # 65^2 seed 3 and 0: mirror-ghost corners with rank-deficient systems
+
+
+@pytest.mark.parametrize("N,periodic,ghosts,deg,reorder", CASES)
+def test_prep_matches_oracle(N, periodic, ghosts, deg, reorder):
+    m = make_mesh(N, L=10.0 if periodic else 1.0, periodic=periodic, seed=3, ghost_layers=ghosts)
+    A = fdu.Prep(m, deg=deg, reorder=reorder).arrays()
+    o = Oracle(m, deg=deg)
+    perm = A["perm"]
+    assert np.array_equal(np.sort(perm[:m.nv_real]), np.arange(m.nv_real))
+    assert np.array_equal(perm[A["iperm"]], np.arange(m.nv))
+    fe = A["flux_edge"]
+    assert np.array_equal(np.sort(fe), o.edges)
+    loc = np.searchsorted(o.edges, fe)
+    assert np.array_equal(perm[A["sten6"]], o.sten6[loc])
+    d = o.s[loc, 3] - o.s[loc, 2]
+    geo_o = np.stack([o.s[loc, 0] / d, o.s[loc, 1] / d, o.s[loc, 4] / d, o.s[loc, 5] / d,
+                      o.dir[loc, 0], o.dir[loc, 1]], 1)
+    np.testing.assert_allclose(A["geo"], geo_o, rtol=0, atol=1e-13)
+    W = o.W
+    for i in range(A["nv_real"]):
+        O = perm[i]
+        a0, a1 = A["vptr"][i], A["vptr"][i + 1]
+        b0, b1 = W["vptr"][O], W["vptr"][O + 1]
+        cols = perm[A["vcol"][a0:a1]]
+        srt = np.argsort(cols)
+        assert np.array_equal(cols[srt], W["vcol"][b0:b1])
+        e0, e1 = A["eptr"][i], A["eptr"][i + 1]
+        f0, f1 = W["eptr"][O], W["eptr"][O + 1]
+        ecols = fe[A["ecol"][e0:e1]]
+        esrt = np.argsort(ecols)
+        assert np.array_equal(ecols[esrt], W["ecol"][f0:f1])
+        scale = max(np.abs(W["wf"][b0:b1]).max(), np.abs(W["wg"][b0:b1]).max(), np.abs(W["we"][f0:f1]).max())
+        err = max(np.abs(A["wfg"][a0:a1][srt, 0] - W["wf"][b0:b1]).max(),
+                  np.abs(A["wfg"][a0:a1][srt, 1] - W["wg"][b0:b1]).max(),
+                  np.abs(A["we"][e0:e1][esrt] - W["we"][f0:f1]).max())
+        assert err <= 1e-12 * scale, (i, err / scale)
+    if ghosts:
+        np.testing.assert_array_equal(perm[A["ghost_src"]], m.ghost_src)
+
+
+@pytest.mark.parametrize("N,diag", [(65, "random"), (33, "uniform")])
+def test_rank_deficient_corner_weights(N, diag):
+    """Exactly symmetric mirror-ghost corners make the least-squares matrix rank
+    deficient; the pivoted-QR row must equal the truncated-SVD pseudo-inverse row."""
+    from oracle.lsq import Topology, ls_weights
+    m = make_mesh(N, L=1.0, periodic=False, seed=0, ghost_layers=4, diag=diag)
+    A = fdu.Prep(m, deg=5, reorder=0).arrays()
+    topo = Topology(m)
+    for O in [0, N - 1, N * (N - 1), N * N - 1]:
+        W = ls_weights(m, topo, [O], 5)
+        a0, a1 = A["vptr"][O], A["vptr"][O + 1]
+        e0, e1 = A["eptr"][O], A["eptr"][O + 1]
+        scale = np.abs(W["we"]).max()
+        assert np.abs(A["wfg"][a0:a1, 0] - W["wf"]).max() <= 1e-12 * scale
+        assert np.abs(A["wfg"][a0:a1, 1] - W["wg"]).max() <= 1e-12 * scale
+        assert np.abs(A["we"][e0:e1] - W["we"]).max() <= 1e-12 * scale
+
+
+def test_regular_mesh_prep_sizes():
+    m = make_mesh(16, L=1.0, periodic=True, jitter=0.0, diag="uniform")
+    A = fdu.Prep(m, deg=5).arrays()
+    assert np.all(np.diff(A["vptr"]) == 18) and np.all(np.diff(A["eptr"]) == 42)
+    np.testing.assert_allclose(A["geo"][:, :4], np.tile([-2.5, -1.5, 1.5, 2.5], (A["ne_flux"], 1)), atol=1e-13)
+
+
+def test_prep_rejects_bad_input():
+    m = make_mesh(8, L=1.0, periodic=True)
+    bad = m.edges.copy()
+    bad[3, 1] = m.nv + 5
+    m2 = type(m)(**{**m.__dict__, "edges": bad})
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        fdu.Prep(m2, deg=3)
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        fdu.Prep(m, deg=9)

@@ -1,0 +1,238 @@
+"""GPU parity of the HIP residual path (called through the C ABI) against the
+FP64 oracle: residual, edge fluxes, CFL step, SSP-RK3 steps, parameter
+switches, reproducibility, small/ragged meshes, and sampled vertices at the
+1M-vertex size.  Tolerance: 1e-12 relative per component (max-norm of the
+difference over the max-norm of the oracle's values)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.solver import Oracle
+from paper_2102_12933_amd.inputs import make_mesh, sod_state, vortex_state
+from tests._helpers import rel_err_per_component
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _fdu():
+    from paper_2102_12933_amd import fdu
+    return fdu
+
+
+def perturbed_sod(m, seed=0, amp=0.05):
+    """Rotated Sod data plus a smooth perturbation, so both the constant-state
+    (beta = 0) and the generic WENO paths are exercised."""
+    w = sod_state(m)
+    x, y = m.xy[:, 0], m.xy[:, 1]
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.5, 1.5, 4)
+    bump = amp * np.stack([np.sin(2 * np.pi * a[0] * x) * np.cos(2 * np.pi * a[1] * y),
+                           np.cos(2 * np.pi * a[2] * x), np.sin(2 * np.pi * a[3] * y), np.zeros_like(x)], 1)
+    w = w.copy()
+    w[:, 0] *= 1 + bump[:, 0]
+    w[:, 1] += bump[:, 1] * w[:, 0]
+    w[:, 2] += bump[:, 2] * w[:, 0]
+    w[:, 3] *= 1 + 0.5 * bump[:, 0]
+    return w
+
+
+class Case:
+    def __init__(self, N, periodic, ghosts, deg, state, reorder=1, seed=0, **params):
+        fdu = _fdu()
+        L = 10.0 if periodic else 1.0
+        self.m = make_mesh(N, L=L, periodic=periodic, seed=seed, ghost_layers=ghosts)
+        self.prep = fdu.Prep(self.m, deg=deg, reorder=reorder)
+        self.A = self.prep.arrays()
+        self.perm = self.A["perm"]
+        self.s = fdu.Solver(self.prep, device=0, **params)
+        okw = {}
+        if "weno_power" in params:
+            okw["weno_power"] = params["weno_power"]
+        if "riemann" in params:
+            okw["riemann"] = "roe" if params["riemann"] == 0 else "rusanov"
+        if "positivity" in params:
+            okw["positivity"] = bool(params["positivity"])
+        self.o = Oracle(self.m, deg=deg, **okw)
+        self.w0 = vortex_state(self.m, beta=5.0, mach=0.5) if state == "vortex" else perturbed_sod(self.m)
+
+    def w_dev(self, w=None):
+        w = self.w0 if w is None else w
+        return torch.from_numpy(np.ascontiguousarray(w[self.perm])).cuda()
+
+
+@pytest.fixture(scope="module")
+def vortex33_p3():
+    return Case(33, True, 0, 3, "vortex")
+
+
+@pytest.fixture(scope="module")
+def vortex33_p5():
+    return Case(33, True, 0, 5, "vortex")
+
+
+@pytest.fixture(scope="module")
+def sod24_p5():
+    return Case(24, False, 4, 5, "sod")
+
+
+def _residual_err(c):
+    R = c.s.residual(c.w_dev()).cpu().numpy()
+    Ro = c.o.residual(torch.from_numpy(c.w0)).numpy()[c.perm[:c.m.nv_real]]
+    return rel_err_per_component(R, Ro)
+
+
+def test_residual_vortex_lowest_pair(vortex33_p3):
+    err = _residual_err(vortex33_p3)
+    print("vortex 33^2 deg 3 rel err per component", err)
+    assert err.max() <= TOL
+
+
+def test_residual_vortex_two_level(vortex33_p5):
+    err = _residual_err(vortex33_p5)
+    print("vortex 33^2 deg 5 rel err per component", err)
+    assert err.max() <= TOL
+
+
+def test_residual_sod_with_walls(sod24_p5):
+    err = _residual_err(sod24_p5)
+    print("sod 24^2 + ghosts rel err per component", err)
+    assert err.max() <= TOL
+
+
+def test_ghost_fill(sod24_p5):
+    c = sod24_p5
+    w = c.w_dev()
+    w[c.m.nv_real:] = 0.0
+    c.s.fill_ghosts(w)
+    ref = c.o.fill_ghosts(torch.from_numpy(c.w0)).numpy()[c.perm]
+    np.testing.assert_array_equal(w.cpu().numpy(), ref)
+
+
+def test_edge_fluxes(vortex33_p5, sod24_p5):
+    for c in (vortex33_p5, sod24_p5):
+        w = c.w_dev()
+        c.s.fill_ghosts(w)
+        r = c.s.edge_fluxes(w).cpu().numpy()
+        ro = c.o.edge_fluxes(torch.from_numpy(c.w0)).numpy()
+        loc = np.searchsorted(c.o.edges, c.A["flux_edge"])
+        err = rel_err_per_component(r, ro[loc])
+        print("edge flux rel err", err)
+        assert err.max() <= TOL
+
+
+def test_cfl_dt(vortex33_p3, sod24_p5):
+    for c in (vortex33_p3, sod24_p5):
+        dt = c.s.cfl_dt(c.w_dev(), 0.5).item()
+        ref = c.o.cfl_dt(torch.from_numpy(c.w0), 0.5)
+        assert abs(dt - ref) <= 1e-14 * ref
+
+
+def test_rk3_ten_steps_config1(vortex33_p3):
+    """Periodic 33^2 vortex, lowest-order pair, CFL 0.5, 10 SSP-RK3 steps."""
+    c = vortex33_p3
+    w = c.w_dev()
+    scratch = torch.empty(2 * c.m.nv, 4, dtype=torch.float64, device="cuda")
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    wo = torch.from_numpy(c.w0.copy())
+    for _ in range(10):
+        c.s.rk_step(w, scratch, dt, cfl=0.5)
+        wo = c.o.rk3_step(wo, c.o.cfl_dt(wo, 0.5))
+    err = rel_err_per_component(w.cpu().numpy(), wo.numpy()[c.perm])
+    print("10 steps rel err", err)
+    assert err.max() <= 1e-12
+
+
+def test_rk_stage_matches_oracle_stage(sod24_p5):
+    c = sod24_p5
+    dtv = 1e-3
+    dt = torch.full((1,), dtv, dtype=torch.float64, device="cuda")
+    wn = c.w_dev()
+    wp = c.w_dev(c.w0 * 1.001)
+    out = torch.empty_like(wn)
+    for k in range(3):
+        c.s.rk_stage(k, wn, wp, out, dt)
+        ref = c.o.rk3_stage(k, torch.from_numpy(c.w0), torch.from_numpy(c.w0 * 1.001), dtv).numpy()[c.perm]
+        nr = c.m.nv_real
+        err = rel_err_per_component(out.cpu().numpy()[:nr], ref[:nr])
+        assert err.max() <= 1e-14, (k, err)
+
+
+@pytest.mark.parametrize("params", [dict(weno_power=2), dict(riemann=1), dict(positivity=0)])
+def test_parameter_switches(params):
+    c = Case(20, True, 0, 5, "vortex", **params)
+    err = _residual_err(c)
+    print(params, err)
+    assert err.max() <= TOL
+
+
+def test_natural_order_and_smallest_meshes():
+    for N, per, G, deg, reo in [(12, True, 0, 5, 0), (13, True, 0, 3, 1), (9, False, 4, 5, 1), (10, False, 4, 3, 0)]:
+        c = Case(N, per, G, deg, "vortex" if per else "sod", reorder=reo, seed=N)
+        err = _residual_err(c)
+        assert err.max() <= TOL, (N, per, err)
+
+
+def test_bitwise_reproducible(vortex33_p5):
+    c = vortex33_p5
+    a = c.s.residual(c.w_dev()).cpu()
+    b = c.s.residual(c.w_dev()).cpu()
+    assert torch.equal(a, b)
+
+
+def test_errors_are_status_codes():
+    fdu = _fdu()
+    s = fdu.Solver(None, device=0)
+    w = torch.zeros(4, 4, dtype=torch.float64, device="cuda")
+    with pytest.raises(fdu.FduError, match="STATE"):
+        fdu._call("fdu_residual", s.handle, None, None, None)
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        s.upload(4, 4, np.zeros((1, 6), np.int32) + 7, np.zeros((1, 6)), [0, 0, 0, 0, 0], [], np.zeros((0, 2)),
+                 [0, 0, 0, 0, 0], [], [], np.ones(4))
+    del w
+
+
+@pytest.mark.slow
+def test_full_size_sod_sampled():
+    """1025^2 rotated Sod (1.05M real vertices) in the bench's launch shape: one
+    SSP-RK3 step from the initial state on the GPU; then the residual of the
+    stepped state and the first stage of a second step are compared with the
+    oracle at sampled vertices (near the interface, at random, walls, corners)."""
+    fdu = _fdu()
+    m = make_mesh(1025, L=1.0, periodic=False, seed=0, ghost_layers=4)
+    prep = fdu.Prep(m, deg=5, reorder=1)
+    perm = prep.arrays()["perm"]
+    s = fdu.Solver(prep, device=0)
+    w0 = torch.from_numpy(sod_state(m)[perm]).cuda()
+    w1, w2, w3 = (torch.empty_like(w0) for _ in range(3))
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    s.cfl_dt(w0, 0.2, dt)
+    s.rk_stage(0, w0, w0, w1, dt)
+    s.rk_stage(1, w0, w1, w2, dt)
+    s.rk_stage(2, w0, w2, w3, dt)
+    R = s.residual(w3).cpu().numpy()
+    s.cfl_dt(w3, 0.2, dt)
+    s.rk_stage(0, w3, w3, w1, dt)
+    st1 = w1.cpu().numpy()
+    w_in = np.empty((m.nv, 4))
+    w_in[perm] = w3.cpu().numpy()
+    iperm = np.argsort(perm)
+    rng = np.random.default_rng(0)
+    a = np.deg2rad(30.0)
+    sd = (m.xy[:m.nv_real, 0] - 0.5) * np.cos(a) + (m.xy[:m.nv_real, 1] - 0.5) * np.sin(a)
+    near = np.nonzero(np.abs(sd) < 0.01)[0]
+    wall = np.nonzero((m.xy[:m.nv_real, 1] < 1e-12) | (m.xy[:m.nv_real, 1] > 1 - 1e-12))[0]
+    sample = np.unique(np.concatenate([rng.choice(near, 300, replace=False), rng.choice(m.nv_real, 100, replace=False),
+                                       rng.choice(wall, 50, replace=False),
+                                       [0, 1024, 1025 * 1024, m.nv_real - 1, 512, 1025 * 512]]))
+    o = Oracle(m, deg=5, vertices=sample)
+    Ro = o.residual(torch.from_numpy(w_in)).numpy()
+    err = rel_err_per_component(R[iperm[sample]], Ro)
+    print("1025^2 sampled residual rel err", err, "sample", len(sample))
+    assert err.max() <= TOL
+    dto = o.cfl_dt(torch.from_numpy(w_in), 0.2)
+    assert abs(dt.item() - dto) <= 1e-14 * dto
+    ref1 = w_in[sample] + dto * Ro
+    err1 = rel_err_per_component(st1[iperm[sample]], ref1)
+    print("first stage rel err", err1)
+    assert err1.max() <= 1e-14
