@@ -194,6 +194,35 @@ fdu_status fdu_rk_stage(fdu_solver* s, int k, const void* w_n, void* w_prev, voi
                         const double* dt_dev, void* stream);
 fdu_status fdu_rk_step(fdu_solver* s, void* w, void* scratch, double cfl, double* dt_dev, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Adjoint (vector-Jacobian products) of the residual and of the SSP-RK3 stage
+ * and step, for gradients through unrolled time stepping.
+ * fdu_enable_adjoint (set-up, synchronous, after fdu_finalize): builds the
+ *   transposed stencil maps on the host and allocates the work buffers
+ *   (about 250 bytes per flux edge plus 32 per vertex).
+ * fdu_residual_vjp: wbar (device [nv_total][4], state dtype) :=
+ *   (dR/dw)^T Rbar for Rbar (device [nv_real][4]); ghost rows of wbar are zero
+ *   (ghost states are copies of real ones and their cotangent is added to the
+ *   source rows).  w's ghost rows are filled (as fdu_residual does); wbar must
+ *   not alias w or Rbar.
+ * fdu_rk_stage_vjp: adjoint of fdu_rk_stage k with the scalar dt:
+ *   wbar_prev := b_k obar + b_k dt (dR/dw_prev)^T obar (ghost rows zero) and,
+ *   for k > 0, wbar_n += a_k obar on the real rows.  obar is [nv_total][4]
+ *   (real rows used).
+ * fdu_rk_step_vjp: adjoint of one fdu_rk_step at a fixed time step (dt on the
+ *   device in dt_dev for the recomputed forward stages, and as the scalar dt):
+ *   recomputes the stage states from w_n (in/out: ghost rows filled) and writes
+ *   wbar_n := (dw_{n+1}/dw_n)^T wbar_np1.  scratch: device, 4 states.
+ * Errors: FDU_ERR_STATE if the adjoint is not enabled; FDU_ERR_INVALID_ARG for
+ * NULL or aliased arguments.  Asynchronous on stream; no allocation.
+ */
+fdu_status fdu_enable_adjoint(fdu_solver* s);
+fdu_status fdu_residual_vjp(fdu_solver* s, void* w, const void* Rbar, void* wbar, void* stream);
+fdu_status fdu_rk_stage_vjp(fdu_solver* s, int k, void* w_prev, const void* obar, void* wbar_n, void* wbar_prev,
+                            double dt, void* stream);
+fdu_status fdu_rk_step_vjp(fdu_solver* s, void* w_n, const void* wbar_np1, void* wbar_n, void* scratch,
+                           const double* dt_dev, double dt, void* stream);
+
 /* fdu_kernel_times: measurement aid.  Launches each kernel of a stage reps
  * times back to back on stream, bracketed by HIP events, and writes the mean
  * duration in milliseconds to avg_ms[0..3] = ghost fill, edge flux, vertex

@@ -1,0 +1,399 @@
+// Adjoint (vector-Jacobian product) of the per-stage residual.
+//
+// Forward, per real vertex O (Sec. 2.2.1 differenced form):
+//   R_O = -( sum_j [wf_Oj (f_j - f_O) + wg_Oj (g_j - g_O)] + sum_k we_Ok r_k )
+//         + cx_O f_O + cy_O g_O,          c_O = sum_k we_Ok n_k,
+// with f_j = f(w_j), g_j = g(w_j) and r_k the edge flux of edge k, a function
+// of the six states of its stencil.  Given a cotangent Rbar on the real
+// vertices, the adjoint is assembled without atomics from transposed maps:
+//   rbar_k  = -sum_{O uses k} we_Ok Rbar_O                      (k_edge_cot)
+//   slots   = (d r_k / d w_{stencil(k)})^T rbar_k, [ne][6][4]     (k_edge_vjp)
+//   fbar_v  = -sum_{O uses v} wf_Ov Rbar_O + [v real] sf_v Rbar_v,
+//   gbar_v  likewise, sf_v = sum_j wf_vj + cx_v,
+//   wbar_v  = (df/dw)^T fbar_v + (dg/dw)^T gbar_v + sum of v's slots  (k_vertex_vjp)
+//   ghosts  copy their mirror source: a ghost's cotangent goes to its source
+//           with the same momentum signs; ghost rows end at zero  (k_ghost_vjp)
+// The edge-flux reverse sweep is written by hand for the NU-WENO5 nonlinear
+// weights and the characteristic projections; the Roe-averaged frame and the
+// Riemann flux (functions of 8 inputs) are differentiated with forward-mode
+// dual numbers.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace fdu {
+
+// a = R^T q (transpose of from_char at a fixed frame)
+__device__ __forceinline__ void from_char_T(const Frame& F, const double qb[4], double ab[4]) {
+  ab[0] = qb[0] + qb[1] * (F.u - F.c * F.nx) + qb[2] * (F.v - F.c * F.ny) + qb[3] * (F.H - F.c * F.un);
+  ab[1] = qb[0] + qb[1] * F.u + qb[2] * F.v + qb[3] * F.q2;
+  ab[2] = -qb[1] * F.ny + qb[2] * F.nx + qb[3] * F.ut;
+  ab[3] = qb[0] + qb[1] * (F.u + F.c * F.nx) + qb[2] * (F.v + F.c * F.ny) + qb[3] * (F.H + F.c * F.un);
+}
+
+// q += L^T o (transpose of to_char at a fixed frame)
+__device__ __forceinline__ void to_char_T_acc(const Frame& F, double gm1, const double ob[4], double qb[4]) {
+  const double ic = 1.0 / F.c;
+  const double b1 = gm1 * ic * ic, b2 = b1 * F.q2;
+  const double coreb = 0.5 * ob[0] - ob[1] + 0.5 * ob[3];
+  const double xb = 0.5 * (ob[0] - ob[3]) * ic;   // cotangent of (u_n rho - n.m)
+  qb[0] += coreb * b2 + xb * F.un + ob[1] - ob[2] * F.ut;
+  qb[1] += -coreb * b1 * F.u - xb * F.nx - ob[2] * F.ny;
+  qb[2] += -coreb * b1 * F.v - xb * F.ny + ob[2] * F.nx;
+  qb[3] += coreb * b1;
+}
+
+// Reverse of weno_eval: ub[m] += vb * d(value)/d(u[m]).
+__device__ __forceinline__ void weno_eval_T(const WenoGeom& G, const double u[5], double eps, int power, double vb,
+                                            double ub[5]) {
+  double ut[3], d1[3], d2[3], be[3], b[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double u0 = u[k], u1 = u[k + 1], u2 = u[k + 2];
+    ut[k] = G.I[k][0] * u0 + G.I[k][1] * u1 + G.I[k][2] * u2;
+    d1[k] = G.D1[k][0] * u0 + G.D1[k][1] * u1 + G.D1[k][2] * u2;
+    d2[k] = G.D2[k][0] * u0 + G.D2[k][1] * u1 + G.D2[k][2] * u2;
+    be[k] = d1[k] * d1[k] + (13.0 / 12.0) * d2[k] * d2[k] + eps;
+    b[k] = power == 2 ? be[k] * be[k] : be[k];
+  }
+  const double n[3] = {G.C[0] * b[1] * b[2], G.C[1] * b[0] * b[2], G.C[2] * b[0] * b[1]};
+  const double iS = 1.0 / (n[0] + n[1] + n[2]);
+  const double value = (n[0] * ut[0] + n[1] * ut[1] + n[2] * ut[2]) * iS;
+  double nb[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) nb[k] = (ut[k] - value) * iS * vb;
+  double bb[3];
+  bb[0] = nb[1] * G.C[1] * b[2] + nb[2] * G.C[2] * b[1];
+  bb[1] = nb[0] * G.C[0] * b[2] + nb[2] * G.C[2] * b[0];
+  bb[2] = nb[0] * G.C[0] * b[1] + nb[1] * G.C[1] * b[0];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double betab = power == 2 ? bb[k] * 2.0 * be[k] : bb[k];
+    const double d1b = betab * 2.0 * d1[k], d2b = betab * (13.0 / 6.0) * d2[k];
+    const double utb = n[k] * iS * vb;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) ub[k + m] += utb * G.I[k][m] + d1b * G.D1[k][m] + d2b * G.D2[k][m];
+  }
+}
+
+using D8 = Dual<8>;
+
+// rbar_k = -sum_{O uses k} we_Ok Rbar_O (transposed edge CSR)
+template <class T, class TW>
+__global__ void __launch_bounds__(256) k_edge_cot(const int* __restrict__ tptr, const int* __restrict__ trow,
+                                                  const TW* __restrict__ tw, const T* __restrict__ Rbar,
+                                                  double* __restrict__ rbar, int ne) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ne) return;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int p = tptr[k]; p < tptr[k + 1]; ++p) {
+    double q[4];
+    load4(Rbar, trow[p], q);
+    const double c = (double)tw[p];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] -= c * q[i];
+  }
+  double2* o = reinterpret_cast<double2*>(rbar + 4 * (size_t)k);
+  o[0] = make_double2(a[0], a[1]);
+  o[1] = make_double2(a[2], a[3]);
+}
+
+// Per flux edge: cotangents of its six stencil states, slots[e][s][4].
+template <class T, class TG>
+__global__ void __launch_bounds__(256) k_edge_vjp(const T* __restrict__ w, const int* __restrict__ sten,
+                                                  const TG* __restrict__ geo, const double* __restrict__ rbar,
+                                                  double* __restrict__ slots, int ne, Scheme S) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  int id[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) id[k] = sten[6 * (size_t)e + k];
+  double W[6][4];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) load4(w, id[k], W[k]);
+  double g[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = (double)geo[6 * (size_t)e + k];
+  const double nx = g[4], ny = g[5];
+  double ob[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) ob[k] = rbar[4 * (size_t)e + k];
+
+  // ---- forward recomputation
+  const Frame F = roe_frame<double>(W[2], W[3], nx, ny, S.gm1);
+  double Cv[6][4];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) to_char(F, S.gm1, W[k], Cv[k]);
+  WenoGeom GL, GR;
+  weno_geom(g[0], g[1], g[2], GL);
+  weno_geom(-g[3], -g[2], -g[1], GR);
+  double cl[4], cr[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double ul[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
+    const double ur[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
+    cl[c] = weno_eval(GL, ul, S.eps, S.power);
+    cr[c] = weno_eval(GR, ur, S.eps, S.power);
+  }
+  double wl[4], wr[4];
+  from_char(F, cl, wl);
+  from_char(F, cr, wr);
+  bool fl = false, fr = false;
+  if (S.positivity) {
+    fl = !physical(wl, S.gm1);
+    fr = !physical(wr, S.gm1);
+    if (fl)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wl[k] = W[2][k];
+    if (fr)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wr[k] = W[3][k];
+  }
+
+  double Wb[6][4];
+#pragma unroll
+  for (int s = 0; s < 6; ++s)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Wb[s][k] = 0.0;
+
+  // ---- Riemann flux: Jacobian by dual numbers over (wl, wr)
+  double wlb[4], wrb[4];
+  {
+    D8 a[4], b[4], o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k] = D8(wl[k]);
+      a[k].d[k] = 1.0;
+      b[k] = D8(wr[k]);
+      b[k].d[4 + k] = 1.0;
+    }
+    riemann_flux<D8>(a, b, nx, ny, S, o);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double sl = 0.0, sr = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        sl += ob[i] * o[i].d[k];
+        sr += ob[i] * o[i].d[4 + k];
+      }
+      wlb[k] = sl;
+      wrb[k] = sr;
+    }
+  }
+  if (fl) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Wb[2][k] += wlb[k];
+  }
+  if (fr) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Wb[3][k] += wrb[k];
+  }
+
+  // ---- back-projection and WENO, at the fixed frame
+  double clb[4] = {0.0, 0.0, 0.0, 0.0}, crb[4] = {0.0, 0.0, 0.0, 0.0};
+  if (!fl) from_char_T(F, wlb, clb);
+  if (!fr) from_char_T(F, wrb, crb);
+  double Cb[6][4];
+#pragma unroll
+  for (int s = 0; s < 6; ++s)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Cb[s][k] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double ul[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
+    const double ur[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
+    double ubl[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, ubr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    weno_eval_T(GL, ul, S.eps, S.power, clb[c], ubl);
+    weno_eval_T(GR, ur, S.eps, S.power, crb[c], ubr);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Cb[m][c] += ubl[m];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Cb[5 - m][c] += ubr[m];
+  }
+  // characteristic projection at the fixed frame
+#pragma unroll
+  for (int s = 0; s < 6; ++s) to_char_T_acc(F, S.gm1, Cb[s], Wb[s]);
+
+  // ---- frame dependence on the end states (W[2], W[3]) by dual numbers
+  {
+    D8 a[4], b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k] = D8(W[2][k]);
+      a[k].d[k] = 1.0;
+      b[k] = D8(W[3][k]);
+      b[k].d[4 + k] = 1.0;
+    }
+    const FrameT<D8> Fd = roe_frame<D8>(a, b, nx, ny, S.gm1);
+    double fb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    auto acc = [&](const D8 o[4], const double cot[4]) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t += cot[i] * o[i].d[j];
+        fb[j] += t;
+      }
+    };
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      D8 q[4], o[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q[k] = D8(W[s][k]);
+      to_char<D8>(Fd, S.gm1, q, o);
+      acc(o, Cb[s]);
+    }
+    if (!fl) {
+      D8 q[4], o[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q[k] = D8(cl[k]);
+      from_char<D8>(Fd, q, o);
+      acc(o, wlb);
+    }
+    if (!fr) {
+      D8 q[4], o[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q[k] = D8(cr[k]);
+      from_char<D8>(Fd, q, o);
+      acc(o, wrb);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Wb[2][k] += fb[k];
+      Wb[3][k] += fb[4 + k];
+    }
+  }
+  double* out = slots + 24 * (size_t)e;
+#pragma unroll
+  for (int s = 0; s < 6; ++s)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[4 * s + k] = Wb[s][k];
+}
+
+// Per vertex (real and ghost): flux-cotangent gathers over the transposed
+// vertex CSR, the flux Jacobian transposes, and the edge slots that read it.
+template <class T, class TW>
+__global__ void __launch_bounds__(256) k_vertex_vjp(const T* __restrict__ w, const T* __restrict__ Rbar,
+                                                    const int* __restrict__ tptr, const int* __restrict__ trow,
+                                                    const TW* __restrict__ twfg, const double* __restrict__ sfg,
+                                                    const int* __restrict__ sptr, const int* __restrict__ scol,
+                                                    const double* __restrict__ slots, int nreal, int nv,
+                                                    double gm1, double* __restrict__ tmp) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  double fb[4] = {0.0, 0.0, 0.0, 0.0}, gb[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int p = tptr[v]; p < tptr[v + 1]; ++p) {
+    double q[4];
+    load4(Rbar, trow[p], q);
+    const double a = (double)twfg[2 * (size_t)p], b = (double)twfg[2 * (size_t)p + 1];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      fb[i] -= a * q[i];
+      gb[i] -= b * q[i];
+    }
+  }
+  if (v < nreal) {
+    double q[4];
+    load4(Rbar, v, q);
+    const double a = sfg[2 * (size_t)v], b = sfg[2 * (size_t)v + 1];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      fb[i] += a * q[i];
+      gb[i] += b * q[i];
+    }
+  }
+  double wb[4] = {0.0, 0.0, 0.0, 0.0};
+  {
+    double q0[4];
+    load4(w, v, q0);
+    Dual<4> q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      q[k] = Dual<4>(q0[k]);
+      q[k].d[k] = 1.0;
+    }
+    const Dual<4> ir = 1.0 / q[0];
+    const Dual<4> u = q[1] * ir, vv = q[2] * ir;
+    const Dual<4> p = gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * vv));
+    const Dual<4> f[4] = {q[1], q[1] * u + p, q[1] * vv, (q[3] + p) * u};
+    const Dual<4> g[4] = {q[2], q[2] * u, q[2] * vv + p, (q[3] + p) * vv};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) t += fb[i] * f[i].d[k] + gb[i] * g[i].d[k];
+      wb[k] = t;
+    }
+  }
+  for (int p = sptr[v]; p < sptr[v + 1]; ++p) {
+    const double2* sp = reinterpret_cast<const double2*>(slots + 4 * (size_t)scol[p]);
+    const double2 a = sp[0], b = sp[1];
+    wb[0] += a.x; wb[1] += a.y; wb[2] += b.x; wb[3] += b.y;
+  }
+  double2* o = reinterpret_cast<double2*>(tmp + 4 * (size_t)v);
+  o[0] = make_double2(wb[0], wb[1]);
+  o[1] = make_double2(wb[2], wb[3]);
+}
+
+// Real rows: own cotangent plus those of the ghosts copied from them (with the
+// ghost's momentum signs); ghost rows: zero.  out = alpha * result + beta * add
+// (add may be null), the form the Runge-Kutta stage adjoint needs.
+template <class T>
+__global__ void __launch_bounds__(256) k_ghost_vjp(const double* __restrict__ tmp, const int* __restrict__ gptr,
+                                                   const int* __restrict__ gcol, const signed char* __restrict__ refl,
+                                                   int nreal, int nv, double alpha, const T* __restrict__ add,
+                                                   double beta, T* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  if (v < nreal) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = tmp[4 * (size_t)v + k];
+    for (int p = gptr[v]; p < gptr[v + 1]; ++p) {
+      const int gi = gcol[p];
+      const double* t = tmp + 4 * (size_t)(nreal + gi);
+      const int f = refl[gi];
+      a[0] += t[0];
+      a[1] += (f & 1) ? -t[1] : t[1];
+      a[2] += (f & 2) ? -t[2] : t[2];
+      a[3] += t[3];
+    }
+  }
+  double r[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[k] = alpha * a[k];
+  if (add != nullptr && v < nreal) {
+    double q[4];
+    load4(add, v, q);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] += beta * q[k];
+  }
+  store4(out, v, r);
+}
+
+// out[v] += a * x[v] on the real rows (ghost rows untouched)
+template <class T>
+__global__ void __launch_bounds__(256) k_axpy_real(T* __restrict__ out, double a, const T* __restrict__ x, int nreal) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nreal) return;
+  double q[4], o[4];
+  load4(x, v, q);
+  load4(out, v, o);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o[k] += a * q[k];
+  store4(out, v, o);
+}
+
+// out[v] = a * x[v] on all rows
+template <class T>
+__global__ void __launch_bounds__(256) k_scale(T* __restrict__ out, double a, const T* __restrict__ x, int nv) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  double q[4];
+  load4(x, v, q);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] *= a;
+  store4(out, v, q);
+}
+
+}  // namespace fdu

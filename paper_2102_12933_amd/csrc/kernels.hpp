@@ -100,22 +100,104 @@ __device__ __forceinline__ double weno_eval(const WenoGeom& G, const double u[5]
 }
 
 // ----------------------------------------------------------------------------
+// Forward-mode dual numbers: value plus N directional derivatives.  The frame
+// and flux functions below are templates on the scalar type so the adjoint
+// kernels can take exact Jacobians of them (N = 8: the two states they read).
+using ::fabs;
+using ::sqrt;
+
+template <int N>
+struct Dual {
+  double v;
+  double d[N];
+  __device__ __forceinline__ Dual() {}
+  __device__ __forceinline__ Dual(double x) : v(x) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) d[i] = 0.0;
+  }
+};
+template <int N>
+__device__ __forceinline__ Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = a.v + b.v;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = a.v - b.v;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator-(const Dual<N>& a) {
+  Dual<N> r; r.v = -a.v;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = a.v * b.v;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; const double ib = 1.0 / b.v; r.v = a.v * ib;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) * ib;
+  return r;
+}
+template <int N> __device__ __forceinline__ Dual<N> operator+(const Dual<N>& a, double b) { return a + Dual<N>(b); }
+template <int N> __device__ __forceinline__ Dual<N> operator+(double a, const Dual<N>& b) { return Dual<N>(a) + b; }
+template <int N> __device__ __forceinline__ Dual<N> operator-(const Dual<N>& a, double b) { return a - Dual<N>(b); }
+template <int N> __device__ __forceinline__ Dual<N> operator-(double a, const Dual<N>& b) { return Dual<N>(a) - b; }
+template <int N>
+__device__ __forceinline__ Dual<N> operator*(const Dual<N>& a, double b) {
+  Dual<N> r; r.v = a.v * b;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b;
+  return r;
+}
+template <int N> __device__ __forceinline__ Dual<N> operator*(double a, const Dual<N>& b) { return b * a; }
+template <int N> __device__ __forceinline__ Dual<N> operator/(const Dual<N>& a, double b) { return a * (1.0 / b); }
+template <int N> __device__ __forceinline__ Dual<N> operator/(double a, const Dual<N>& b) { return Dual<N>(a) / b; }
+template <int N>
+__device__ __forceinline__ Dual<N> sqrt(const Dual<N>& a) {
+  Dual<N> r; r.v = ::sqrt(a.v); const double h = 0.5 / r.v;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * h;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> fabs(const Dual<N>& a) { return a.v < 0.0 ? -a : a; }
+__device__ __forceinline__ double val(double x) { return x; }
+template <int N> __device__ __forceinline__ double val(const Dual<N>& x) { return x.v; }
+
+// ----------------------------------------------------------------------------
 // Eigenvectors of A_n = n_x df/dw + n_y dg/dw at a Roe-averaged state:
 // columns (1, u - c n, H - c u_n), (1, u, q^2/2), (0, t, u_t), (1, u + c n, H + c u_n),
 // t = (-n_y, n_x); the left eigenvectors in closed form.
-struct Frame {
-  double u, v, H, c, un, ut, q2, nx, ny;
+template <class T>
+struct FrameT {
+  T u, v, H, c, un, ut, q2;
+  double nx, ny;
 };
+using Frame = FrameT<double>;
 
-__device__ __forceinline__ Frame roe_frame(const double a[4], const double b[4], double nx, double ny, double gm1) {
-  Frame F;
-  const double ra = sqrt(a[0]), rb = sqrt(b[0]);
-  const double ia = 1.0 / a[0], ib = 1.0 / b[0];
-  const double ua = a[1] * ia, va = a[2] * ia, ub = b[1] * ib, vb = b[2] * ib;
-  const double pa = gm1 * (a[3] - 0.5 * (a[1] * ua + a[2] * va));
-  const double pb = gm1 * (b[3] - 0.5 * (b[1] * ub + b[2] * vb));
-  const double Ha = (a[3] + pa) * ia, Hb = (b[3] + pb) * ib;
-  const double is = 1.0 / (ra + rb);
+template <class T>
+__device__ __forceinline__ FrameT<T> roe_frame(const T a[4], const T b[4], double nx, double ny, double gm1) {
+  FrameT<T> F;
+  const T ra = sqrt(a[0]), rb = sqrt(b[0]);
+  const T ia = 1.0 / a[0], ib = 1.0 / b[0];
+  const T ua = a[1] * ia, va = a[2] * ia, ub = b[1] * ib, vb = b[2] * ib;
+  const T pa = gm1 * (a[3] - 0.5 * (a[1] * ua + a[2] * va));
+  const T pb = gm1 * (b[3] - 0.5 * (b[1] * ub + b[2] * vb));
+  const T Ha = (a[3] + pa) * ia, Hb = (b[3] + pb) * ib;
+  const T is = 1.0 / (ra + rb);
   F.u = (ra * ua + rb * ub) * is;
   F.v = (ra * va + rb * vb) * is;
   F.H = (ra * Ha + rb * Hb) * is;
@@ -124,18 +206,19 @@ __device__ __forceinline__ Frame roe_frame(const double a[4], const double b[4],
   F.nx = nx;
   F.ny = ny;
   F.un = F.u * nx + F.v * ny;
-  F.ut = -F.u * ny + F.v * nx;
+  F.ut = F.v * nx - F.u * ny;
   return F;
 }
 
 // characteristic variables l_k . q
-__device__ __forceinline__ void to_char(const Frame& F, double gm1, const double q[4], double o[4]) {
-  const double ic = 1.0 / F.c;
-  const double b1 = gm1 * ic * ic, b2 = b1 * F.q2;
-  const double mv = F.u * q[1] + F.v * q[2];            // u . m
-  const double nm = F.nx * q[1] + F.ny * q[2];          // n . m
-  const double tm = -F.ny * q[1] + F.nx * q[2];         // t . m
-  const double core = b2 * q[0] - b1 * mv + b1 * q[3];  // b2 rho - b1 u.m + b1 rhoE
+template <class T>
+__device__ __forceinline__ void to_char(const FrameT<T>& F, double gm1, const T q[4], T o[4]) {
+  const T ic = 1.0 / F.c;
+  const T b1 = gm1 * ic * ic, b2 = b1 * F.q2;
+  const T mv = F.u * q[1] + F.v * q[2];                 // u . m
+  const T nm = F.nx * q[1] + F.ny * q[2];               // n . m
+  const T tm = F.nx * q[2] - F.ny * q[1];               // t . m
+  const T core = b2 * q[0] - b1 * mv + b1 * q[3];       // b2 rho - b1 u.m + b1 rhoE
   o[0] = 0.5 * (core + (F.un * q[0] - nm) * ic);
   o[1] = q[0] - core;
   o[2] = tm - F.ut * q[0];
@@ -143,8 +226,9 @@ __device__ __forceinline__ void to_char(const Frame& F, double gm1, const double
 }
 
 // conservative variables sum_k a_k r_k
-__device__ __forceinline__ void from_char(const Frame& F, const double a[4], double q[4]) {
-  const double s = a[0] + a[3], d = a[3] - a[0];
+template <class T>
+__device__ __forceinline__ void from_char(const FrameT<T>& F, const T a[4], T q[4]) {
+  const T s = a[0] + a[3], d = a[3] - a[0];
   q[0] = s + a[1];
   q[1] = F.u * (s + a[1]) + F.c * F.nx * d - F.ny * a[2];
   q[2] = F.v * (s + a[1]) + F.c * F.ny * d + F.nx * a[2];
@@ -160,48 +244,50 @@ __device__ __forceinline__ bool physical(const double q[4], double gm1) {
   return p > 0.0;
 }
 
-__device__ __forceinline__ double harten(double l, double delta) {
-  const double a = fabs(l);
-  return a < delta ? (l * l + delta * delta) / (2.0 * delta) : a;
+template <class T>
+__device__ __forceinline__ T harten(const T& l, const T& delta) {
+  const T a = fabs(l);
+  return val(a) < val(delta) ? (l * l + delta * delta) / (2.0 * delta) : a;
 }
 
-__device__ __forceinline__ void normal_flux(const double q[4], double nx, double ny, double gm1, double F[4],
-                                            double* un_out = nullptr, double* c2_out = nullptr) {
-  const double ir = 1.0 / q[0];
-  const double u = q[1] * ir, v = q[2] * ir;
-  const double p = gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * v));
-  const double un = u * nx + v * ny;
+template <class T>
+__device__ __forceinline__ void normal_flux(const T q[4], double nx, double ny, double gm1, T F[4], T& un, T& c2) {
+  const T ir = 1.0 / q[0];
+  const T u = q[1] * ir, v = q[2] * ir;
+  const T p = gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * v));
+  un = u * nx + v * ny;
   F[0] = q[0] * un;
   F[1] = q[1] * un + p * nx;
   F[2] = q[2] * un + p * ny;
   F[3] = (q[3] + p) * un;
-  if (un_out) *un_out = un;
-  if (c2_out) *c2_out = (gm1 + 1.0) * p * ir;
+  c2 = (gm1 + 1.0) * p * ir;
 }
 
 // Numerical flux along the edge direction n from the midpoint states wl, wr.
-__device__ __forceinline__ void riemann_flux(const double wl[4], const double wr[4], double nx, double ny,
-                                             const Scheme& S, double out[4]) {
-  double Fl[4], Fr[4], unl, unr, c2l, c2r;
-  normal_flux(wl, nx, ny, S.gm1, Fl, &unl, &c2l);
-  normal_flux(wr, nx, ny, S.gm1, Fr, &unr, &c2r);
+template <class T>
+__device__ __forceinline__ void riemann_flux(const T wl[4], const T wr[4], double nx, double ny, const Scheme& S,
+                                             T out[4]) {
+  T Fl[4], Fr[4], unl, unr, c2l, c2r;
+  normal_flux(wl, nx, ny, S.gm1, Fl, unl, c2l);
+  normal_flux(wr, nx, ny, S.gm1, Fr, unr, c2r);
   if (S.riemann == 1) {
-    const double s = fmax(fabs(unl) + sqrt(c2l), fabs(unr) + sqrt(c2r));
+    const T sl = fabs(unl) + sqrt(c2l), sr = fabs(unr) + sqrt(c2r);
+    const T sm = val(sl) >= val(sr) ? sl : sr;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[k] = 0.5 * (Fl[k] + Fr[k]) - 0.5 * s * (wr[k] - wl[k]);
+    for (int k = 0; k < 4; ++k) out[k] = 0.5 * (Fl[k] + Fr[k]) - 0.5 * sm * (wr[k] - wl[k]);
     return;
   }
-  const Frame F = roe_frame(wl, wr, nx, ny, S.gm1);
-  double dq[4], a[4];
+  const FrameT<T> F = roe_frame(wl, wr, nx, ny, S.gm1);
+  T dq[4], a[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) dq[k] = wr[k] - wl[k];
   to_char(F, S.gm1, dq, a);
-  const double delta = S.efrac * F.c;
-  a[0] *= harten(F.un - F.c, delta);
-  a[1] *= harten(F.un, delta);
-  a[2] *= harten(F.un, delta);
-  a[3] *= harten(F.un + F.c, delta);
-  double d[4];
+  const T delta = S.efrac * F.c;
+  a[0] = a[0] * harten(F.un - F.c, delta);
+  a[1] = a[1] * harten(F.un, delta);
+  a[2] = a[2] * harten(F.un, delta);
+  a[3] = a[3] * harten(F.un + F.c, delta);
+  T d[4];
   from_char(F, a, d);
 #pragma unroll
   for (int k = 0; k < 4; ++k) out[k] = 0.5 * (Fl[k] + Fr[k]) - 0.5 * d[k];
@@ -250,7 +336,7 @@ __global__ void __launch_bounds__(256) k_edge_flux(const T* __restrict__ w, cons
   const double nx = g[4], ny = g[5];
 
   // characteristic frame at the Roe average of the edge's end states
-  const Frame F = roe_frame(W[2], W[3], nx, ny, S.gm1);
+  const Frame F = roe_frame<double>(W[2], W[3], nx, ny, S.gm1);
   double Cv[6][4];
 #pragma unroll
   for (int k = 0; k < 6; ++k) to_char(F, S.gm1, W[k], Cv[k]);
@@ -279,7 +365,7 @@ __global__ void __launch_bounds__(256) k_edge_flux(const T* __restrict__ w, cons
       for (int k = 0; k < 4; ++k) wr[k] = W[3][k];
   }
   double out[4];
-  riemann_flux(wl, wr, nx, ny, S, out);
+  riemann_flux<double>(wl, wr, nx, ny, S, out);
   double2* rp = reinterpret_cast<double2*>(r + 4 * (size_t)e);
   rp[0] = make_double2(out[0], out[1]);
   rp[1] = make_double2(out[2], out[3]);

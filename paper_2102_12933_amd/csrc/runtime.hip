@@ -9,6 +9,7 @@
 
 #include "fdu_internal.h"
 #include "kernels.hpp"
+#include "adjoint.hpp"
 
 namespace fdu {
 
@@ -55,9 +56,16 @@ struct fdu_solver {
   fdu_params params{};
   int64_t nv_total = 0, nv_real = 0, ne_flux = 0, nnz_v = 0, nnz_e = 0, ng = 0;
   bool have_edges = false, have_vertices = false, finalized = false;
-  // host copies kept until finalize (c_O needs the edge directions and weights)
-  std::vector<double> h_geo, h_we;
-  std::vector<int32_t> h_eptr, h_ecol;
+  // host copies (c_O needs the edge directions and weights; the adjoint's
+  // transposed maps need the stencils)
+  std::vector<double> h_geo, h_we, h_wfg, h_cO;
+  std::vector<int32_t> h_eptr, h_ecol, h_vptr, h_vcol, h_sten, h_gsrc;
+  std::vector<int8_t> h_grefl;
+  // adjoint: transposed maps and work buffers (fdu_enable_adjoint)
+  bool adjoint = false;
+  DevBuf<int32_t> te_ptr, te_row, tv_ptr, tv_row, ts_ptr, ts_col, tg_ptr, tg_col;
+  DevBuf<double> te_w, tv_wfg, sfg, rbar, slots, vtmp;
+  DevBuf<float> te_w32, tv_wfg32;
   DevBuf<int32_t> sten, vptr, vcol, eptr, ecol, gsrc;
   DevBuf<int8_t> grefl;
   DevBuf<double> geo, wfg, we, cO, hmin, flux, part;
@@ -193,6 +201,155 @@ void rk_step_t(fdu_solver* s, T* w, T* scratch, double cfl, double* dt, hipStrea
   rk_stage_t<T>(s, 2, w, w2, w, dt, st);
 }
 
+// Transposed maps for the adjoint, built on the host from the uploaded
+// stencils; entries of each list are in increasing order of their source index.
+void build_adjoint(fdu_solver* s) {
+  const int64_t nv = s->nv_total, nr = s->nv_real, ne = s->ne_flux, ng = s->ng;
+  auto csr = [](int64_t n, const std::vector<int32_t>& keys, std::vector<int32_t>& ptr, std::vector<int32_t>& ord) {
+    ptr.assign(n + 1, 0);
+    for (int32_t k : keys) ptr[k + 1]++;
+    for (int64_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    ord.assign(keys.size(), 0);
+    for (size_t p = 0; p < keys.size(); ++p) ord[fill[keys[p]]++] = (int32_t)p;
+  };
+  std::vector<int32_t> ptr, ord, rowof;
+  // edge -> (vertex O, we_Ok)
+  rowof.resize(s->h_ecol.size());
+  for (int64_t v = 0; v < nr; ++v)
+    for (int32_t p = s->h_eptr[v]; p < s->h_eptr[v + 1]; ++p) rowof[p] = (int32_t)v;
+  csr(ne, s->h_ecol, ptr, ord);
+  std::vector<int32_t> row(ord.size());
+  std::vector<double> wv(ord.size());
+  for (size_t i = 0; i < ord.size(); ++i) { row[i] = rowof[ord[i]]; wv[i] = s->h_we[ord[i]]; }
+  s->te_ptr.upload(ptr.data(), ptr.size());
+  s->te_row.upload(row.data(), row.size());
+  // vertex j -> (vertex O, wf_Oj, wg_Oj)
+  rowof.resize(s->h_vcol.size());
+  for (int64_t v = 0; v < nr; ++v)
+    for (int32_t p = s->h_vptr[v]; p < s->h_vptr[v + 1]; ++p) rowof[p] = (int32_t)v;
+  csr(nv, s->h_vcol, ptr, ord);
+  std::vector<int32_t> vrow(ord.size());
+  std::vector<double> vw(2 * ord.size());
+  for (size_t i = 0; i < ord.size(); ++i) {
+    vrow[i] = rowof[ord[i]];
+    vw[2 * i] = s->h_wfg[2 * (size_t)ord[i]];
+    vw[2 * i + 1] = s->h_wfg[2 * (size_t)ord[i] + 1];
+  }
+  s->tv_ptr.upload(ptr.data(), ptr.size());
+  s->tv_row.upload(vrow.data(), vrow.size());
+  if (s->prec == FDU_F64) {
+    s->te_w.upload(wv.data(), wv.size());
+    s->tv_wfg.upload(vw.data(), vw.size());
+  } else {
+    std::vector<float> a(wv.begin(), wv.end()), b(vw.begin(), vw.end());
+    s->te_w32.upload(a.data(), a.size());
+    s->tv_wfg32.upload(b.data(), b.size());
+  }
+  // sf_O = sum_j wf_Oj + cx_O, sg_O likewise
+  std::vector<double> sf(2 * nr, 0.0);
+  for (int64_t v = 0; v < nr; ++v) {
+    double a = s->h_cO[2 * v], b = s->h_cO[2 * v + 1];
+    for (int32_t p = s->h_vptr[v]; p < s->h_vptr[v + 1]; ++p) {
+      a += s->h_wfg[2 * (size_t)p];
+      b += s->h_wfg[2 * (size_t)p + 1];
+    }
+    sf[2 * v] = a;
+    sf[2 * v + 1] = b;
+  }
+  s->sfg.upload(sf.data(), sf.size());
+  // vertex -> edge slots (e * 6 + position) that read it
+  csr(nv, s->h_sten, ptr, ord);
+  s->ts_ptr.upload(ptr.data(), ptr.size());
+  s->ts_col.upload(ord.data(), ord.size());
+  // real vertex -> ghosts copied from it
+  csr(nr, s->h_gsrc, ptr, ord);
+  s->tg_ptr.upload(ptr.data(), ptr.size());
+  if (ord.empty()) ord.push_back(0);
+  s->tg_col.upload(ord.data(), ord.size());
+  if (ng == 0 && s->grefl.n == 0) {
+    int8_t z = 0;
+    s->grefl.upload(&z, 1);
+  }
+  s->rbar.alloc(4 * ne);
+  s->slots.alloc(24 * ne);
+  s->vtmp.alloc(4 * nv);
+  s->adjoint = true;
+}
+
+void ready_adjoint(const fdu_solver* s) {
+  ready(s);
+  if (!s->adjoint) throw Error(FDU_ERR_STATE, "adjoint not enabled (fdu_enable_adjoint)");
+}
+
+// out = alpha (dR/dw)^T Rbar + beta add (real rows of add; add may be null);
+// ghost rows of out are zero.  w's ghost rows are filled first.
+template <class T>
+void residual_vjp_t(fdu_solver* s, T* w, const T* Rbar, T* out, double alpha, const T* add, double beta,
+                    hipStream_t st) {
+  const Scheme S = scheme_of(s);
+  const int ne = (int)s->ne_flux, nv = (int)s->nv_total, nr = (int)s->nv_real;
+  fill_ghosts_t<T>(s, w, st);
+  if (s->prec == FDU_F64) {
+    hipLaunchKernelGGL((k_edge_cot<T, double>), dim3(nblocks(ne)), dim3(256), 0, st, s->te_ptr.p, s->te_row.p,
+                       s->te_w.p, Rbar, s->rbar.p, ne);
+    hipLaunchKernelGGL((k_edge_vjp<T, double>), dim3(nblocks(ne)), dim3(256), 0, st, w, s->sten.p, s->geo.p,
+                       s->rbar.p, s->slots.p, ne, S);
+    hipLaunchKernelGGL((k_vertex_vjp<T, double>), dim3(nblocks(nv)), dim3(256), 0, st, w, Rbar, s->tv_ptr.p,
+                       s->tv_row.p, s->tv_wfg.p, s->sfg.p, s->ts_ptr.p, s->ts_col.p, s->slots.p, nr, nv, S.gm1,
+                       s->vtmp.p);
+  } else {
+    hipLaunchKernelGGL((k_edge_cot<T, float>), dim3(nblocks(ne)), dim3(256), 0, st, s->te_ptr.p, s->te_row.p,
+                       s->te_w32.p, Rbar, s->rbar.p, ne);
+    hipLaunchKernelGGL((k_edge_vjp<T, float>), dim3(nblocks(ne)), dim3(256), 0, st, w, s->sten.p, s->geo32.p,
+                       s->rbar.p, s->slots.p, ne, S);
+    hipLaunchKernelGGL((k_vertex_vjp<T, float>), dim3(nblocks(nv)), dim3(256), 0, st, w, Rbar, s->tv_ptr.p,
+                       s->tv_row.p, s->tv_wfg32.p, s->sfg.p, s->ts_ptr.p, s->ts_col.p, s->slots.p, nr, nv, S.gm1,
+                       s->vtmp.p);
+  }
+  launch_check();
+  hipLaunchKernelGGL(k_ghost_vjp<T>, dim3(nblocks(nv)), dim3(256), 0, st, s->vtmp.p, s->tg_ptr.p, s->tg_col.p,
+                     reinterpret_cast<const signed char*>(s->grefl.p), nr, nv, alpha, add, beta, out);
+  launch_check();
+}
+
+// Adjoint of stage k: given obar (cotangent of the stage output's real rows),
+// wbar_prev := b_k obar + b_k dt (dR/dw_prev)^T obar and wbar_n += a_k obar.
+template <class T>
+void rk_stage_vjp_t(fdu_solver* s, int k, T* wprev, const T* obar, T* wbar_n, T* wbar_prev, double dt,
+                    hipStream_t st) {
+  const double a = kRK[k][0], b = kRK[k][1];
+  residual_vjp_t<T>(s, wprev, obar, wbar_prev, b * dt, obar, b, st);
+  if (a != 0.0) {
+    hipLaunchKernelGGL(k_axpy_real<T>, dim3(nblocks(s->nv_real)), dim3(256), 0, st, wbar_n, a, obar,
+                       (int)s->nv_real);
+    launch_check();
+  }
+}
+
+// Adjoint of one SSP-RK3 step at a fixed dt: recompute the stage states from
+// w_n, then run the stages backwards.  scratch holds 4 states.
+template <class T>
+void rk_step_vjp_t(fdu_solver* s, T* wn, const T* wbar_np1, T* wbar_n, T* scratch, const double* dt_dev, double dt,
+                   hipStream_t st) {
+  const size_t S4 = 4 * (size_t)s->nv_total;
+  T* w1 = scratch;
+  T* w2 = scratch + S4;
+  T* g2 = scratch + 2 * S4;
+  T* g1 = scratch + 3 * S4;
+  rk_stage_t<T>(s, 0, wn, wn, w1, dt_dev, st);
+  rk_stage_t<T>(s, 1, wn, w1, w2, dt_dev, st);
+  // wbar_n := 1/3 wbar_np1 (real rows), ghost rows 0
+  hipLaunchKernelGGL(k_scale<T>, dim3(nblocks(s->nv_total)), dim3(256), 0, st, wbar_n, 0.0, wbar_np1,
+                     (int)s->nv_total);
+  launch_check();
+  rk_stage_vjp_t<T>(s, 2, w2, wbar_np1, wbar_n, g2, dt, st);
+  rk_stage_vjp_t<T>(s, 1, w1, g2, wbar_n, g1, dt, st);
+  rk_stage_vjp_t<T>(s, 0, wn, g1, wbar_n, g2, dt, st);
+  hipLaunchKernelGGL(k_axpy_real<T>, dim3(nblocks(s->nv_real)), dim3(256), 0, st, wbar_n, 1.0, g2, (int)s->nv_real);
+  launch_check();
+}
+
 }  // namespace
 
 extern "C" {
@@ -259,7 +416,9 @@ fdu_status fdu_upload_edge_stencils(fdu_solver* s, int64_t nv_total, int64_t nv_
     s->ne_flux = ne_flux;
     s->ng = nv_total - nv_real;
     s->sten.upload(sten6, 6 * ne_flux);
+    s->h_sten.assign(sten6, sten6 + 6 * ne_flux);
     s->h_geo.assign(geo, geo + 6 * ne_flux);
+    s->adjoint = false;
     if (s->prec == FDU_F64) {
       s->geo.upload(geo, 6 * ne_flux);
     } else {
@@ -302,8 +461,14 @@ fdu_status fdu_upload_vertex_stencils(fdu_solver* s, const int32_t* vptr, const 
     s->h_eptr.assign(eptr, eptr + s->nv_real + 1);
     s->h_ecol.assign(ecol, ecol + nnz_e);
     s->h_we.assign(we, we + nnz_e);
-    if (s->prec == FDU_F32)  // c_O must use the weights the kernels see
+    s->h_vptr.assign(vptr, vptr + s->nv_real + 1);
+    s->h_vcol.assign(vcol, vcol + nnz_v);
+    s->h_wfg.assign(wfg, wfg + 2 * nnz_v);
+    if (s->prec == FDU_F32) {  // c_O and the adjoint must use the weights the kernels see
       for (auto& x : s->h_we) x = (double)(float)x;
+      for (auto& x : s->h_wfg) x = (double)(float)x;
+    }
+    s->adjoint = false;
     s->have_vertices = true;
   });
 }
@@ -321,8 +486,11 @@ fdu_status fdu_upload_ghosts(fdu_solver* s, int64_t ng, const int32_t* ghost_src
     }
     DeviceGuard dg(s->device);
     s->finalized = false;
+    s->adjoint = false;
     s->gsrc.upload(ghost_src, ng);
     s->grefl.upload(ghost_refl, ng);
+    s->h_gsrc.assign(ghost_src, ghost_src + ng);
+    s->h_grefl.assign(ghost_refl, ghost_refl + ng);
   });
 }
 
@@ -359,6 +527,7 @@ fdu_status fdu_finalize(fdu_solver* s) {
         c[2 * v + 1] += s->h_we[p] * ny;
       }
     s->cO.upload(c.data(), c.size());
+    s->h_cO = c;
     s->cfl_blocks = (int)std::min<int64_t>(1024, (s->nv_real + 255) / 256);
     s->part.alloc(s->cfl_blocks);
     s->finalized = true;
@@ -450,6 +619,63 @@ fdu_status fdu_rk_step(fdu_solver* s, void* w, void* scratch, double cfl, double
       rk_step_t<double>(s, (double*)w, (double*)scratch, cfl, dt_dev, (hipStream_t)stream);
     else
       rk_step_t<float>(s, (float*)w, (float*)scratch, cfl, dt_dev, (hipStream_t)stream);
+  });
+}
+
+fdu_status fdu_enable_adjoint(fdu_solver* s) {
+  return guard([&] {
+    ready(s);
+    DeviceGuard dg(s->device);
+    build_adjoint(s);
+  });
+}
+
+fdu_status fdu_residual_vjp(fdu_solver* s, void* w, const void* Rbar, void* wbar, void* stream) {
+  return guard([&] {
+    ready_adjoint(s);
+    need(w && Rbar && wbar, "NULL argument");
+    need(wbar != w && wbar != Rbar, "wbar must not alias w or Rbar");
+    DeviceGuard dg(s->device);
+    if (s->prec == FDU_F64)
+      residual_vjp_t<double>(s, (double*)w, (const double*)Rbar, (double*)wbar, 1.0, nullptr, 0.0,
+                             (hipStream_t)stream);
+    else
+      residual_vjp_t<float>(s, (float*)w, (const float*)Rbar, (float*)wbar, 1.0, nullptr, 0.0, (hipStream_t)stream);
+  });
+}
+
+fdu_status fdu_rk_stage_vjp(fdu_solver* s, int k, void* w_prev, const void* obar, void* wbar_n, void* wbar_prev,
+                            double dt, void* stream) {
+  return guard([&] {
+    ready_adjoint(s);
+    need(k >= 0 && k <= 2, "stage must be 0, 1 or 2");
+    need(w_prev && obar && wbar_prev && (k == 0 || wbar_n), "NULL argument");
+    need(wbar_prev != obar && wbar_prev != w_prev && wbar_prev != wbar_n, "wbar_prev must not alias other arrays");
+    need(std::isfinite(dt), "dt must be finite");
+    DeviceGuard dg(s->device);
+    if (s->prec == FDU_F64)
+      rk_stage_vjp_t<double>(s, k, (double*)w_prev, (const double*)obar, (double*)wbar_n, (double*)wbar_prev, dt,
+                             (hipStream_t)stream);
+    else
+      rk_stage_vjp_t<float>(s, k, (float*)w_prev, (const float*)obar, (float*)wbar_n, (float*)wbar_prev, dt,
+                            (hipStream_t)stream);
+  });
+}
+
+fdu_status fdu_rk_step_vjp(fdu_solver* s, void* w_n, const void* wbar_np1, void* wbar_n, void* scratch,
+                           const double* dt_dev, double dt, void* stream) {
+  return guard([&] {
+    ready_adjoint(s);
+    need(w_n && wbar_np1 && wbar_n && scratch && dt_dev, "NULL argument");
+    need(wbar_n != wbar_np1, "wbar_n must not alias wbar_np1");
+    need(std::isfinite(dt), "dt must be finite");
+    DeviceGuard dg(s->device);
+    if (s->prec == FDU_F64)
+      rk_step_vjp_t<double>(s, (double*)w_n, (const double*)wbar_np1, (double*)wbar_n, (double*)scratch, dt_dev, dt,
+                            (hipStream_t)stream);
+    else
+      rk_step_vjp_t<float>(s, (float*)w_n, (const float*)wbar_np1, (float*)wbar_n, (float*)scratch, dt_dev, dt,
+                           (hipStream_t)stream);
   });
 }
 

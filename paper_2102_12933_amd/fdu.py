@@ -62,6 +62,10 @@ _SIGS = {
     "fdu_rk_stage": (I32, [VP, I32, VP, VP, VP, VP, VP]),
     "fdu_rk_step": (I32, [VP, VP, VP, D, VP, VP]),
     "fdu_kernel_times": (I32, [VP, VP, VP, I32, VP, VP]),
+    "fdu_enable_adjoint": (I32, [VP]),
+    "fdu_residual_vjp": (I32, [VP, VP, VP, VP, VP]),
+    "fdu_rk_stage_vjp": (I32, [VP, I32, VP, VP, VP, VP, D, VP]),
+    "fdu_rk_step_vjp": (I32, [VP, VP, VP, VP, VP, VP, D, VP]),
 }
 
 _lib = None
@@ -246,6 +250,29 @@ class Solver:
             raise ValueError("scratch must hold two states")
         _call("fdu_rk_step", self.handle, self._state(w), C.c_void_p(scratch.data_ptr()), float(cfl),
               self._dt(dt), _stream())
+
+    # -- adjoint
+    def enable_adjoint(self):
+        _call("fdu_enable_adjoint", self.handle)
+
+    def residual_vjp(self, w, Rbar, out=None):
+        if out is None:
+            out = torch.empty(self.nv_total, 4, dtype=self.dtype, device=w.device)
+        _call("fdu_residual_vjp", self.handle, self._state(w), self._state(Rbar, self.nv_real), self._state(out),
+              _stream())
+        return out
+
+    def rk_stage_vjp(self, k, w_prev, obar, wbar_n, wbar_prev, dt: float):
+        wn = self._state(wbar_n) if wbar_n is not None else None
+        _call("fdu_rk_stage_vjp", self.handle, int(k), self._state(w_prev), self._state(obar), wn,
+              self._state(wbar_prev), float(dt), _stream())
+
+    def rk_step_vjp(self, w_n, wbar_np1, wbar_n, scratch, dt_dev, dt: float):
+        if not (scratch.is_cuda and scratch.dtype == self.dtype and scratch.is_contiguous()
+                and scratch.numel() >= 16 * self.nv_total):
+            raise ValueError("scratch must hold four states")
+        _call("fdu_rk_step_vjp", self.handle, self._state(w_n), self._state(wbar_np1), self._state(wbar_n),
+              C.c_void_p(scratch.data_ptr()), self._dt(dt_dev), float(dt), _stream())
 
     def kernel_times(self, w, reps: int = 20):
         """Mean kernel durations in ms: ghost fill, edge flux, vertex step, CFL."""
