@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=30)
     ap.add_argument("--cfl", type=float, default=SOD_CFL)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the run, copy a 512 MiB buffer 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -138,6 +140,11 @@ def main():
     w0 = torch.from_numpy(np.ascontiguousarray(sod_state(mesh)[perm])).cuda()
     w1, w2, w3 = (torch.empty_like(w0) for _ in range(3))
     dt = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    solver.fill_ghosts(w0)
+    tune = solver.autotune(w0, reps=args.kernel_reps)
+    log(f"autotune: edge variants {['%.1f us' % (t * 1e3) for t in tune['edge_ms']]} -> {tune['edge']}, "
+        f"vertex variants {['%.1f us' % (t * 1e3) for t in tune['vertex_ms']]} -> {tune['vertex']}")
 
     def step():
         solver.cfl_dt(w0, args.cfl, dt)
@@ -171,7 +178,8 @@ def main():
         ms = kt[k]
         kern[k] = dict(avg_ms=ms, bytes=nb[k], gbs=nb[k] / (ms * 1e-3) / 1e9)
     dom = max(("edge", "vertex"), key=lambda k: kt[k])
-    names = dict(edge="k_edge_flux", vertex="k_vertex")
+    names = dict(edge=["k_edge_flux", "k_edge_flux_lean"][tune["edge"]],
+                 vertex="k_vertex" if tune["vertex"] == 0 else "k_vertex_pipe")
     traffic = traffic_from_profiles(names[dom], args.N)
     achieved = kern[dom]["gbs"]
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -200,6 +208,9 @@ def main():
         "roofline": roofline,
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in d.items()}
                     for k, d in kern.items()} | {"ghost_ms": round(kt["ghost"], 5), "cfl_ms": round(kt["cfl"], 5)},
+        "autotune": {"edge_variant": tune["edge"], "vertex_variant": tune["vertex"],
+                     "edge_ms": [round(t, 5) for t in tune["edge_ms"]],
+                     "vertex_ms": [round(t, 5) for t in tune["vertex_ms"]]},
     }
     if not args.no_cpu_baseline:
         w_in = np.empty((mesh.nv, 4))
@@ -207,6 +218,12 @@ def main():
         log("cpu baseline (oracle on a bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline(mesh, w_in)
     print(json.dumps(out), flush=True)
+    if args.calib_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -233,6 +233,23 @@ fdu_status fdu_rk_step_vjp(fdu_solver* s, void* w_n, const void* wbar_np1, void*
  * The timed work equals the work of the corresponding compute calls. */
 fdu_status fdu_kernel_times(fdu_solver* s, void* w, void* scratch, int reps, double* avg_ms, void* stream);
 
+/* Kernel variants and autotuning.  Every variant computes the same residual
+ * (the parity tests run each one); they differ in schedule and register use:
+ *   edge:   0 = coefficient-form WENO, IEEE divisions; 1 = divided-difference
+ *           WENO, one side's geometry live at a time, refined reciprocals;
+ *   vertex: 0 = 16 lanes per vertex, strided loops; 1, 2, 3 = 16, 32, 8 lanes
+ *           per vertex, all index/weight loads issued before all gathers;
+ *           4, 5 = strided loops with 8 and 4 lanes per vertex; 6, 7 = strided
+ *           loops with 16 and 8 lanes and non-temporal stencil-array loads.
+ * fdu_set_variants / fdu_get_variants select and report them (n_edge, n_vertex:
+ * how many exist).  fdu_autotune times every edge variant and then every vertex
+ * variant on the given state with fdu_kernel_times (reps launches each),
+ * writes the mean times (ms) to times_ms[0 .. n_edge + n_vertex - 1] and keeps
+ * the fastest of each; synchronous; w and scratch as for fdu_kernel_times. */
+fdu_status fdu_set_variants(fdu_solver* s, int edge_variant, int vertex_variant);
+fdu_status fdu_get_variants(const fdu_solver* s, int* edge_variant, int* vertex_variant, int* n_edge, int* n_vertex);
+fdu_status fdu_autotune(fdu_solver* s, void* w, void* scratch, int reps, double* times_ms, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,79 @@
+"""torch.autograd bindings of the library's hand-written adjoint.
+
+ResidualFn   R = residual(w); backward calls fdu_residual_vjp.
+RKUnroll     w_N = N SSP-RK3 steps at a fixed dt from w_0; the forward keeps a
+             state every ``ckpt_every`` steps, the backward recomputes the states
+             of each segment from its checkpoint and applies fdu_rk_step_vjp
+             (which itself recomputes the stage states) in reverse.
+
+Every forward and backward pass runs in the HIP library; these classes only
+hold tensors and order the calls.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class ResidualFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, w, solver):
+        w_in = w.detach().contiguous().clone()      # the library fills ghost rows in place
+        R = solver.residual(w_in)
+        ctx.save_for_backward(w_in)
+        ctx.solver = solver
+        return R
+
+    @staticmethod
+    def backward(ctx, Rbar):
+        (w_in,) = ctx.saved_tensors
+        wbar = ctx.solver.residual_vjp(w_in.clone(), Rbar.contiguous())
+        return wbar, None
+
+
+class RKUnroll(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, w0, solver, nsteps: int, dt: float, ckpt_every: int = 5):
+        dev = w0.device
+        w = w0.detach().contiguous().clone()
+        scratch = torch.empty(2 * solver.nv_total, 4, dtype=w.dtype, device=dev)
+        dt_dev = torch.full((1,), float(dt), dtype=torch.float64, device=dev)
+        ckpts = [w.clone()]
+        for i in range(nsteps):
+            solver.rk_step(w, scratch, dt_dev)
+            if (i + 1) % ckpt_every == 0 and i + 1 < nsteps:
+                ckpts.append(w.clone())
+        ctx.solver, ctx.nsteps, ctx.dt, ctx.ckpt_every = solver, nsteps, float(dt), ckpt_every
+        ctx.save_for_backward(*ckpts)
+        return w
+
+    @staticmethod
+    def backward(ctx, wbar):
+        solver, nsteps, dt, every = ctx.solver, ctx.nsteps, ctx.dt, ctx.ckpt_every
+        ckpts = ctx.saved_tensors
+        dev = wbar.device
+        dt_dev = torch.full((1,), dt, dtype=torch.float64, device=dev)
+        scratch2 = torch.empty(2 * solver.nv_total, 4, dtype=wbar.dtype, device=dev)
+        scratch4 = torch.empty(4 * solver.nv_total, 4, dtype=wbar.dtype, device=dev)
+        g = wbar.contiguous().clone()
+        g[solver.nv_real:] = 0.0
+        gn = torch.empty_like(g)
+        for seg in reversed(range(len(ckpts))):
+            start = seg * every
+            stop = min(start + every, nsteps)
+            states = [ckpts[seg].clone()]
+            w = ckpts[seg].clone()
+            for _ in range(start, stop - 1):
+                solver.rk_step(w, scratch2, dt_dev)
+                states.append(w.clone())
+            for j in reversed(range(stop - start)):
+                solver.rk_step_vjp(states[j], g, gn, scratch4, dt_dev, dt)
+                g, gn = gn, g
+        return g, None, None, None, None
+
+
+def residual(solver, w):
+    return ResidualFn.apply(w, solver)
+
+
+def rk_unroll(solver, w0, nsteps: int, dt: float, ckpt_every: int = 5):
+    return RKUnroll.apply(w0, solver, nsteps, dt, ckpt_every)

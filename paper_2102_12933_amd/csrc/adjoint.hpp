@@ -24,7 +24,7 @@
 namespace fdu {
 
 // a = R^T q (transpose of from_char at a fixed frame)
-__device__ __forceinline__ void from_char_T(const Frame& F, const double qb[4], double ab[4]) {
+FDU_HD void from_char_T(const Frame& F, const double qb[4], double ab[4]) {
   ab[0] = qb[0] + qb[1] * (F.u - F.c * F.nx) + qb[2] * (F.v - F.c * F.ny) + qb[3] * (F.H - F.c * F.un);
   ab[1] = qb[0] + qb[1] * F.u + qb[2] * F.v + qb[3] * F.q2;
   ab[2] = -qb[1] * F.ny + qb[2] * F.nx + qb[3] * F.ut;
@@ -32,7 +32,7 @@ __device__ __forceinline__ void from_char_T(const Frame& F, const double qb[4], 
 }
 
 // q += L^T o (transpose of to_char at a fixed frame)
-__device__ __forceinline__ void to_char_T_acc(const Frame& F, double gm1, const double ob[4], double qb[4]) {
+FDU_HD void to_char_T_acc(const Frame& F, double gm1, const double ob[4], double qb[4]) {
   const double ic = 1.0 / F.c;
   const double b1 = gm1 * ic * ic, b2 = b1 * F.q2;
   const double coreb = 0.5 * ob[0] - ob[1] + 0.5 * ob[3];
@@ -44,7 +44,7 @@ __device__ __forceinline__ void to_char_T_acc(const Frame& F, double gm1, const 
 }
 
 // Reverse of weno_eval: ub[m] += vb * d(value)/d(u[m]).
-__device__ __forceinline__ void weno_eval_T(const WenoGeom& G, const double u[5], double eps, int power, double vb,
+FDU_HD void weno_eval_T(const WenoGeom& G, const double u[5], double eps, int power, double vb,
                                             double ub[5]) {
   double ut[3], d1[3], d2[3], be[3], b[3];
 #pragma unroll
@@ -78,47 +78,11 @@ __device__ __forceinline__ void weno_eval_T(const WenoGeom& G, const double u[5]
 
 using D8 = Dual<8>;
 
-// rbar_k = -sum_{O uses k} we_Ok Rbar_O (transposed edge CSR)
-template <class T, class TW>
-__global__ void __launch_bounds__(256) k_edge_cot(const int* __restrict__ tptr, const int* __restrict__ trow,
-                                                  const TW* __restrict__ tw, const T* __restrict__ Rbar,
-                                                  double* __restrict__ rbar, int ne) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= ne) return;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int p = tptr[k]; p < tptr[k + 1]; ++p) {
-    double q[4];
-    load4(Rbar, trow[p], q);
-    const double c = (double)tw[p];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] -= c * q[i];
-  }
-  double2* o = reinterpret_cast<double2*>(rbar + 4 * (size_t)k);
-  o[0] = make_double2(a[0], a[1]);
-  o[1] = make_double2(a[2], a[3]);
-}
-
-// Per flux edge: cotangents of its six stencil states, slots[e][s][4].
-template <class T, class TG>
-__global__ void __launch_bounds__(256) k_edge_vjp(const T* __restrict__ w, const int* __restrict__ sten,
-                                                  const TG* __restrict__ geo, const double* __restrict__ rbar,
-                                                  double* __restrict__ slots, int ne, Scheme S) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
-  int id[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) id[k] = sten[6 * (size_t)e + k];
-  double W[6][4];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) load4(w, id[k], W[k]);
-  double g[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) g[k] = (double)geo[6 * (size_t)e + k];
+// Cotangents Wb of the six stencil states of one edge for the flux cotangent
+// ob (the reverse of edge_flux_one).
+FDU_HD void edge_vjp_one(const double W[6][4], const double g[6], const double ob[4], const Scheme& S,
+                         double Wb[6][4]) {
   const double nx = g[4], ny = g[5];
-  double ob[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) ob[k] = rbar[4 * (size_t)e + k];
-
   // ---- forward recomputation
   const Frame F = roe_frame<double>(W[2], W[3], nx, ny, S.gm1);
   double Cv[6][4];
@@ -150,7 +114,6 @@ __global__ void __launch_bounds__(256) k_edge_vjp(const T* __restrict__ w, const
       for (int k = 0; k < 4; ++k) wr[k] = W[3][k];
   }
 
-  double Wb[6][4];
 #pragma unroll
   for (int s = 0; s < 6; ++s)
 #pragma unroll
@@ -263,6 +226,51 @@ __global__ void __launch_bounds__(256) k_edge_vjp(const T* __restrict__ w, const
       Wb[3][k] += fb[4 + k];
     }
   }
+}
+
+
+
+// rbar_k = -sum_{O uses k} we_Ok Rbar_O (transposed edge CSR)
+template <class T, class TW>
+__global__ void __launch_bounds__(256) k_edge_cot(const int* __restrict__ tptr, const int* __restrict__ trow,
+                                                  const TW* __restrict__ tw, const T* __restrict__ Rbar,
+                                                  double* __restrict__ rbar, int ne) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ne) return;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int p = tptr[k]; p < tptr[k + 1]; ++p) {
+    double q[4];
+    load4(Rbar, trow[p], q);
+    const double c = (double)tw[p];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] -= c * q[i];
+  }
+  double2* o = reinterpret_cast<double2*>(rbar + 4 * (size_t)k);
+  o[0] = make_double2(a[0], a[1]);
+  o[1] = make_double2(a[2], a[3]);
+}
+
+// Per flux edge: cotangents of its six stencil states, slots[e][s][4].
+template <class T, class TG>
+__global__ void __launch_bounds__(256) k_edge_vjp(const T* __restrict__ w, const int* __restrict__ sten,
+                                                  const TG* __restrict__ geo, const double* __restrict__ rbar,
+                                                  double* __restrict__ slots, int ne, Scheme S) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  int id[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) id[k] = sten[6 * (size_t)e + k];
+  double W[6][4];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) load4(w, id[k], W[k]);
+  double g[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = (double)geo[6 * (size_t)e + k];
+  double ob[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) ob[k] = rbar[4 * (size_t)e + k];
+  double Wb[6][4];
+  edge_vjp_one(W, g, ob, S, Wb);
   double* out = slots + 24 * (size_t)e;
 #pragma unroll
   for (int s = 0; s < 6; ++s)

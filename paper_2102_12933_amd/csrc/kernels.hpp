@@ -5,6 +5,10 @@
 
 #include <hip/hip_runtime.h>
 
+// Per-item math is host+device so the host tests can check it on the CPU;
+// memory access and scheduling live in the __global__ kernels only.
+#define FDU_HD __host__ __device__ __forceinline__
+
 namespace fdu {
 
 struct Scheme {
@@ -39,12 +43,21 @@ __device__ __forceinline__ void store4(float* __restrict__ w, int v, const doubl
 }
 
 // Euler fluxes f, g of a conservative state (Sec. 2.1).
-__device__ __forceinline__ void euler_fg(const double q[4], double gm1, double f[4], double g[4]) {
+FDU_HD void euler_fg(const double q[4], double gm1, double f[4], double g[4]) {
   const double ir = 1.0 / q[0];
   const double u = q[1] * ir, v = q[2] * ir;
   const double p = gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * v));
   f[0] = q[1]; f[1] = q[1] * u + p; f[2] = q[1] * v; f[3] = (q[3] + p) * u;
   g[0] = q[2]; g[1] = q[2] * u;     g[2] = q[2] * v + p; g[3] = (q[3] + p) * v;
+}
+
+// Reciprocal: hardware estimate refined by two Newton steps (relative error a
+// few ulp); used where the optimized kernels divide.
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
 }
 
 // ----------------------------------------------------------------------------
@@ -59,7 +72,7 @@ struct WenoGeom {
 };
 
 // x0, x1, x4: the outer nodes (x2 = -1/2, x3 = 1/2).
-__device__ __forceinline__ void weno_geom(double x0, double x1, double x4, WenoGeom& G) {
+FDU_HD void weno_geom(double x0, double x1, double x4, WenoGeom& G) {
   const double x2 = -0.5, x3 = 0.5;
   const double xs[5] = {x0, x1, x2, x3, x4};
 #pragma unroll
@@ -80,7 +93,7 @@ __device__ __forceinline__ void weno_geom(double x0, double x1, double x4, WenoG
 }
 
 // Nonlinear interpolant at 0 from values u[0..4] at the five nodes.
-__device__ __forceinline__ double weno_eval(const WenoGeom& G, const double u[5], double eps, int power) {
+FDU_HD double weno_eval(const WenoGeom& G, const double u[5], double eps, int power) {
   double ut[3], b[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -110,72 +123,72 @@ template <int N>
 struct Dual {
   double v;
   double d[N];
-  __device__ __forceinline__ Dual() {}
-  __device__ __forceinline__ Dual(double x) : v(x) {
+  FDU_HD Dual() {}
+  FDU_HD Dual(double x) : v(x) {
 #pragma unroll
     for (int i = 0; i < N; ++i) d[i] = 0.0;
   }
 };
 template <int N>
-__device__ __forceinline__ Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) {
+FDU_HD Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) {
   Dual<N> r; r.v = a.v + b.v;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i];
   return r;
 }
 template <int N>
-__device__ __forceinline__ Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) {
+FDU_HD Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) {
   Dual<N> r; r.v = a.v - b.v;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i];
   return r;
 }
 template <int N>
-__device__ __forceinline__ Dual<N> operator-(const Dual<N>& a) {
+FDU_HD Dual<N> operator-(const Dual<N>& a) {
   Dual<N> r; r.v = -a.v;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
   return r;
 }
 template <int N>
-__device__ __forceinline__ Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) {
+FDU_HD Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) {
   Dual<N> r; r.v = a.v * b.v;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
   return r;
 }
 template <int N>
-__device__ __forceinline__ Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
+FDU_HD Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
   Dual<N> r; const double ib = 1.0 / b.v; r.v = a.v * ib;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) * ib;
   return r;
 }
-template <int N> __device__ __forceinline__ Dual<N> operator+(const Dual<N>& a, double b) { return a + Dual<N>(b); }
-template <int N> __device__ __forceinline__ Dual<N> operator+(double a, const Dual<N>& b) { return Dual<N>(a) + b; }
-template <int N> __device__ __forceinline__ Dual<N> operator-(const Dual<N>& a, double b) { return a - Dual<N>(b); }
-template <int N> __device__ __forceinline__ Dual<N> operator-(double a, const Dual<N>& b) { return Dual<N>(a) - b; }
+template <int N> FDU_HD Dual<N> operator+(const Dual<N>& a, double b) { return a + Dual<N>(b); }
+template <int N> FDU_HD Dual<N> operator+(double a, const Dual<N>& b) { return Dual<N>(a) + b; }
+template <int N> FDU_HD Dual<N> operator-(const Dual<N>& a, double b) { return a - Dual<N>(b); }
+template <int N> FDU_HD Dual<N> operator-(double a, const Dual<N>& b) { return Dual<N>(a) - b; }
 template <int N>
-__device__ __forceinline__ Dual<N> operator*(const Dual<N>& a, double b) {
+FDU_HD Dual<N> operator*(const Dual<N>& a, double b) {
   Dual<N> r; r.v = a.v * b;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b;
   return r;
 }
-template <int N> __device__ __forceinline__ Dual<N> operator*(double a, const Dual<N>& b) { return b * a; }
-template <int N> __device__ __forceinline__ Dual<N> operator/(const Dual<N>& a, double b) { return a * (1.0 / b); }
-template <int N> __device__ __forceinline__ Dual<N> operator/(double a, const Dual<N>& b) { return Dual<N>(a) / b; }
+template <int N> FDU_HD Dual<N> operator*(double a, const Dual<N>& b) { return b * a; }
+template <int N> FDU_HD Dual<N> operator/(const Dual<N>& a, double b) { return a * (1.0 / b); }
+template <int N> FDU_HD Dual<N> operator/(double a, const Dual<N>& b) { return Dual<N>(a) / b; }
 template <int N>
-__device__ __forceinline__ Dual<N> sqrt(const Dual<N>& a) {
+FDU_HD Dual<N> sqrt(const Dual<N>& a) {
   Dual<N> r; r.v = ::sqrt(a.v); const double h = 0.5 / r.v;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * h;
   return r;
 }
 template <int N>
-__device__ __forceinline__ Dual<N> fabs(const Dual<N>& a) { return a.v < 0.0 ? -a : a; }
-__device__ __forceinline__ double val(double x) { return x; }
-template <int N> __device__ __forceinline__ double val(const Dual<N>& x) { return x.v; }
+FDU_HD Dual<N> fabs(const Dual<N>& a) { return a.v < 0.0 ? -a : a; }
+FDU_HD double val(double x) { return x; }
+template <int N> FDU_HD double val(const Dual<N>& x) { return x.v; }
 
 // ----------------------------------------------------------------------------
 // Eigenvectors of A_n = n_x df/dw + n_y dg/dw at a Roe-averaged state:
@@ -189,7 +202,7 @@ struct FrameT {
 using Frame = FrameT<double>;
 
 template <class T>
-__device__ __forceinline__ FrameT<T> roe_frame(const T a[4], const T b[4], double nx, double ny, double gm1) {
+FDU_HD FrameT<T> roe_frame(const T a[4], const T b[4], double nx, double ny, double gm1) {
   FrameT<T> F;
   const T ra = sqrt(a[0]), rb = sqrt(b[0]);
   const T ia = 1.0 / a[0], ib = 1.0 / b[0];
@@ -212,7 +225,7 @@ __device__ __forceinline__ FrameT<T> roe_frame(const T a[4], const T b[4], doubl
 
 // characteristic variables l_k . q
 template <class T>
-__device__ __forceinline__ void to_char(const FrameT<T>& F, double gm1, const T q[4], T o[4]) {
+FDU_HD void to_char(const FrameT<T>& F, double gm1, const T q[4], T o[4]) {
   const T ic = 1.0 / F.c;
   const T b1 = gm1 * ic * ic, b2 = b1 * F.q2;
   const T mv = F.u * q[1] + F.v * q[2];                 // u . m
@@ -227,7 +240,7 @@ __device__ __forceinline__ void to_char(const FrameT<T>& F, double gm1, const T 
 
 // conservative variables sum_k a_k r_k
 template <class T>
-__device__ __forceinline__ void from_char(const FrameT<T>& F, const T a[4], T q[4]) {
+FDU_HD void from_char(const FrameT<T>& F, const T a[4], T q[4]) {
   const T s = a[0] + a[3], d = a[3] - a[0];
   q[0] = s + a[1];
   q[1] = F.u * (s + a[1]) + F.c * F.nx * d - F.ny * a[2];
@@ -236,7 +249,7 @@ __device__ __forceinline__ void from_char(const FrameT<T>& F, const T a[4], T q[
 }
 
 // rho > 0 and p > 0 (false for NaN as well)
-__device__ __forceinline__ bool physical(const double q[4], double gm1) {
+FDU_HD bool physical(const double q[4], double gm1) {
   if (!(q[0] > 0.0)) return false;
   const double ir = 1.0 / q[0];
   const double u = q[1] * ir, v = q[2] * ir;
@@ -245,13 +258,13 @@ __device__ __forceinline__ bool physical(const double q[4], double gm1) {
 }
 
 template <class T>
-__device__ __forceinline__ T harten(const T& l, const T& delta) {
+FDU_HD T harten(const T& l, const T& delta) {
   const T a = fabs(l);
   return val(a) < val(delta) ? (l * l + delta * delta) / (2.0 * delta) : a;
 }
 
 template <class T>
-__device__ __forceinline__ void normal_flux(const T q[4], double nx, double ny, double gm1, T F[4], T& un, T& c2) {
+FDU_HD void normal_flux(const T q[4], double nx, double ny, double gm1, T F[4], T& un, T& c2) {
   const T ir = 1.0 / q[0];
   const T u = q[1] * ir, v = q[2] * ir;
   const T p = gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * v));
@@ -265,7 +278,7 @@ __device__ __forceinline__ void normal_flux(const T q[4], double nx, double ny, 
 
 // Numerical flux along the edge direction n from the midpoint states wl, wr.
 template <class T>
-__device__ __forceinline__ void riemann_flux(const T wl[4], const T wr[4], double nx, double ny, const Scheme& S,
+FDU_HD void riemann_flux(const T wl[4], const T wr[4], double nx, double ny, const Scheme& S,
                                              T out[4]) {
   T Fl[4], Fr[4], unl, unr, c2l, c2r;
   normal_flux(wl, nx, ny, S.gm1, Fl, unl, c2l);
@@ -291,6 +304,42 @@ __device__ __forceinline__ void riemann_flux(const T wl[4], const T wr[4], doubl
   from_char(F, a, d);
 #pragma unroll
   for (int k = 0; k < 4; ++k) out[k] = 0.5 * (Fl[k] + Fr[k]) - 0.5 * d[k];
+}
+
+// Numerical flux r_k of one edge from its six stencil states W (L3 L2 L1 R1 R2
+// R3) and geometry g (s0/d, s1/d, s4/d, s5/d, n_x, n_y).
+FDU_HD void edge_flux_one(const double W[6][4], const double g[6], const Scheme& S, double out[4]) {
+  const double nx = g[4], ny = g[5];
+  // characteristic frame at the Roe average of the edge's end states
+  const Frame F = roe_frame<double>(W[2], W[3], nx, ny, S.gm1);
+  double Cv[6][4];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) to_char(F, S.gm1, W[k], Cv[k]);
+
+  // left state from (L3 L2 L1 R1 R2); right state from the mirror (R3 R2 R1 L1 L2)
+  WenoGeom GL, GR;
+  weno_geom(g[0], g[1], g[2], GL);
+  weno_geom(-g[3], -g[2], -g[1], GR);
+  double cl[4], cr[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double ul[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
+    const double ur[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
+    cl[c] = weno_eval(GL, ul, S.eps, S.power);
+    cr[c] = weno_eval(GR, ur, S.eps, S.power);
+  }
+  double wl[4], wr[4];
+  from_char(F, cl, wl);
+  from_char(F, cr, wr);
+  if (S.positivity) {
+    if (!physical(wl, S.gm1))
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wl[k] = W[2][k];
+    if (!physical(wr, S.gm1))
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wr[k] = W[3][k];
+  }
+  riemann_flux<double>(wl, wr, nx, ny, S, out);
 }
 
 // Map a hardware block index to a logical one so that each of the 8 XCDs
@@ -333,39 +382,8 @@ __global__ void __launch_bounds__(256) k_edge_flux(const T* __restrict__ w, cons
   double g[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = (double)geo[6 * (size_t)e + k];
-  const double nx = g[4], ny = g[5];
-
-  // characteristic frame at the Roe average of the edge's end states
-  const Frame F = roe_frame<double>(W[2], W[3], nx, ny, S.gm1);
-  double Cv[6][4];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) to_char(F, S.gm1, W[k], Cv[k]);
-
-  // left state from (L3 L2 L1 R1 R2); right state from the mirror (R3 R2 R1 L1 L2)
-  WenoGeom GL, GR;
-  weno_geom(g[0], g[1], g[2], GL);
-  weno_geom(-g[3], -g[2], -g[1], GR);
-  double cl[4], cr[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const double ul[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
-    const double ur[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
-    cl[c] = weno_eval(GL, ul, S.eps, S.power);
-    cr[c] = weno_eval(GR, ur, S.eps, S.power);
-  }
-  double wl[4], wr[4];
-  from_char(F, cl, wl);
-  from_char(F, cr, wr);
-  if (S.positivity) {
-    if (!physical(wl, S.gm1))
-#pragma unroll
-      for (int k = 0; k < 4; ++k) wl[k] = W[2][k];
-    if (!physical(wr, S.gm1))
-#pragma unroll
-      for (int k = 0; k < 4; ++k) wr[k] = W[3][k];
-  }
   double out[4];
-  riemann_flux<double>(wl, wr, nx, ny, S, out);
+  edge_flux_one(W, g, S, out);
   double2* rp = reinterpret_cast<double2*>(r + 4 * (size_t)e);
   rp[0] = make_double2(out[0], out[1]);
   rp[1] = make_double2(out[2], out[3]);
@@ -375,7 +393,17 @@ __global__ void __launch_bounds__(256) k_edge_flux(const T* __restrict__ w, cons
 // share of the vertex terms wf (f_j - f_O) + wg (g_j - g_O) and of the edge
 // terms we r_k; a butterfly over the LPV lanes reduces them, no atomics.
 // mode 0: R = -div.  mode 1: out = a w_n + b (w_prev + dt (-div)), w_prev = w.
-template <class T, class TW, int LPV>
+// Streaming loads of the stencil arrays (read once per launch); NT marks them
+// non-temporal so they do not displace the gathered states and fluxes in cache.
+template <bool NT, class X>
+__device__ __forceinline__ X ldstream(const X* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
+template <class T, class TW, int LPV, bool NT = false>
 __global__ void __launch_bounds__(256) k_vertex(const T* __restrict__ w, const int* __restrict__ vptr,
                                                 const int* __restrict__ vcol, const TW* __restrict__ wfg,
                                                 const int* __restrict__ eptr, const int* __restrict__ ecol,
@@ -394,8 +422,8 @@ __global__ void __launch_bounds__(256) k_vertex(const T* __restrict__ w, const i
   if (active) {
     const int pe = vptr[v + 1];
     for (int p = vptr[v] + lane; p < pe; p += LPV) {
-      const int j = vcol[p];
-      const double wf = (double)wfg[2 * (size_t)p], wg = (double)wfg[2 * (size_t)p + 1];
+      const int j = ldstream<NT>(vcol + p);
+      const double wf = (double)ldstream<NT>(wfg + 2 * (size_t)p), wg = (double)ldstream<NT>(wfg + 2 * (size_t)p + 1);
       double q[4], f[4], g[4];
       load4(w, j, q);
       euler_fg(q, gm1, f, g);
@@ -404,12 +432,232 @@ __global__ void __launch_bounds__(256) k_vertex(const T* __restrict__ w, const i
     }
     const int qe = eptr[v + 1];
     for (int p = eptr[v] + lane; p < qe; p += LPV) {
-      const int k = ecol[p];
-      const double c = (double)we[p];
+      const int k = ldstream<NT>(ecol + p);
+      const double c = (double)ldstream<NT>(we + p);
       const double2* rp = reinterpret_cast<const double2*>(r + 4 * (size_t)k);
       const double2 x = rp[0], y = rp[1];
       acc[0] += c * x.x; acc[1] += c * x.y; acc[2] += c * y.x; acc[3] += c * y.y;
     }
+  }
+#pragma unroll
+  for (int m = LPV / 2; m >= 1; m >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += __shfl_xor(acc[k], m, LPV);
+  }
+  if (!active || lane != 0) return;
+  const double cx = cO[2 * (size_t)v], cy = cO[2 * (size_t)v + 1];
+  double res[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) res[k] = -(acc[k] - (cx * f0[k] + cy * g0[k]));
+  if (mode == 0) {
+    store4(R, v, res);
+  } else {
+    const double dt = *dt_dev;
+    double n[4] = {0.0, 0.0, 0.0, 0.0};
+    if (a != 0.0) load4(wn, v, n);
+    double o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = a * n[k] + b * (q0[k] + dt * res[k]);
+    store4(out, v, o);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Register-lean WENO: the same interpolants written with divided differences.
+// For a sub-stencil with nodes (a, b, c) and values (ua, ub, uc):
+//   d1 = (ub - ua)/(b - a), d2 = (uc - ub)/(c - b), q'' = 2 (d2 - d1)/(c - a),
+//   q'(0) = d1 - (q''/2)(a + b),  q(0) = ua - d1 a + (q''/2) a b,
+// so a side needs the four inverse node gaps, three inverse double gaps, the
+// nodes and C_k (13 values) instead of 30 coefficients.
+struct WenoDD {
+  double x0, x1, x4;    // outer nodes (x2 = -1/2, x3 = 1/2)
+  double ig[4];         // 1/(x_{m+1} - x_m), m = 0..3 (ig[2] = 1)
+  double ih[3];         // 1/(x_{m+2} - x_m), m = 0..2
+  double C[3];
+};
+
+__device__ __forceinline__ void weno_dd_geom(double x0, double x1, double x4, WenoDD& G) {
+  G.x0 = x0; G.x1 = x1; G.x4 = x4;
+  G.ig[0] = frcp(x1 - x0);
+  G.ig[1] = frcp(-0.5 - x1);
+  G.ig[2] = 1.0;
+  G.ig[3] = frcp(x4 - 0.5);
+  G.ih[0] = frcp(-0.5 - x0);
+  G.ih[1] = frcp(0.5 - x1);
+  G.ih[2] = frcp(x4 + 0.5);
+  const double i40 = frcp(x4 - x0);
+  G.C[0] = 0.5 * x4 * i40 * frcp(0.5 - x0);
+  G.C[2] = x0 * x1 * i40 * frcp(x4 - x1);
+  G.C[1] = 1.0 - G.C[0] - G.C[2];
+}
+
+__device__ __forceinline__ double weno_dd_eval(const WenoDD& G, const double u[5], double eps, int power) {
+  const double xs[5] = {G.x0, G.x1, -0.5, 0.5, G.x4};
+  double dd[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) dd[m] = (u[m + 1] - u[m]) * G.ig[m];
+  double ut[3], b[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double a = xs[k], bb = xs[k + 1];
+    const double h2 = (dd[k + 1] - dd[k]) * G.ih[k];          // q''/2
+    const double d1 = dd[k] - h2 * (a + bb);                   // q'(0)
+    ut[k] = u[k] - dd[k] * a + h2 * a * bb;                    // q(0)
+    const double q2 = 2.0 * h2;
+    b[k] = d1 * d1 + (13.0 / 12.0) * q2 * q2 + eps;
+    if (power == 2) b[k] *= b[k];
+  }
+  const double n0 = G.C[0] * b[1] * b[2];
+  const double n1 = G.C[1] * b[0] * b[2];
+  const double n2 = G.C[2] * b[0] * b[1];
+  return (n0 * ut[0] + n1 * ut[1] + n2 * ut[2]) * frcp(n0 + n1 + n2);
+}
+
+// Edge flux, register-lean variant: one side's WENO geometry live at a time,
+// divided-difference interpolants, refined reciprocals.
+template <class T, class TG>
+__global__ void __launch_bounds__(256) k_edge_flux_lean(const T* __restrict__ w, const int* __restrict__ sten,
+                                                        const TG* __restrict__ geo, double* __restrict__ r, int ne,
+                                                        Scheme S) {
+  const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  int id[6];
+  {
+    const int2* sp = reinterpret_cast<const int2*>(sten + 6 * (size_t)e);
+    int2 a = sp[0], b = sp[1], c = sp[2];
+    id[0] = a.x; id[1] = a.y; id[2] = b.x; id[3] = b.y; id[4] = c.x; id[5] = c.y;
+  }
+  double W2[4], W3[4];
+  load4(w, id[2], W2);
+  load4(w, id[3], W3);
+  double g[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = (double)geo[6 * (size_t)e + k];
+  const double nx = g[4], ny = g[5];
+  const Frame F = roe_frame<double>(W2, W3, nx, ny, S.gm1);
+  double Cv[6][4];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double q[4];
+    if (k == 2) { for (int i = 0; i < 4; ++i) q[i] = W2[i]; }
+    else if (k == 3) { for (int i = 0; i < 4; ++i) q[i] = W3[i]; }
+    else load4(w, id[k], q);
+    to_char(F, S.gm1, q, Cv[k]);
+  }
+  double cl[4], cr[4];
+  {
+    WenoDD G;
+    weno_dd_geom(g[0], g[1], g[2], G);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double u[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
+      cl[c] = weno_dd_eval(G, u, S.eps, S.power);
+    }
+  }
+  {
+    WenoDD G;
+    weno_dd_geom(-g[3], -g[2], -g[1], G);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double u[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
+      cr[c] = weno_dd_eval(G, u, S.eps, S.power);
+    }
+  }
+  double wl[4], wr[4];
+  from_char(F, cl, wl);
+  from_char(F, cr, wr);
+  if (S.positivity) {
+    if (!physical(wl, S.gm1))
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wl[k] = W2[k];
+    if (!physical(wr, S.gm1))
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wr[k] = W3[k];
+  }
+  double out[4];
+  riemann_flux<double>(wl, wr, nx, ny, S, out);
+  double2* rp = reinterpret_cast<double2*>(r + 4 * (size_t)e);
+  rp[0] = make_double2(out[0], out[1]);
+  rp[1] = make_double2(out[2], out[3]);
+}
+
+// Vertex step, software-pipelined: every lane first loads the ids and weights
+// of up to MV vertex entries and ME edge entries, then issues all their gathers,
+// then accumulates; entries beyond MV*LPV / ME*LPV go through a tail loop.
+template <class T, class TW, int LPV, int MV, int ME>
+__global__ void __launch_bounds__(256) k_vertex_pipe(const T* __restrict__ w, const int* __restrict__ vptr,
+                                                     const int* __restrict__ vcol, const TW* __restrict__ wfg,
+                                                     const int* __restrict__ eptr, const int* __restrict__ ecol,
+                                                     const TW* __restrict__ we, const double* __restrict__ cO,
+                                                     const double* __restrict__ r, int nreal, double gm1, int mode,
+                                                     T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
+                                                     double a, double b, const double* __restrict__ dt_dev) {
+  const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int v = t / LPV, lane = t % LPV;
+  const bool active = v < nreal;
+  const int vv = active ? v : 0;
+  int vb = 0, ve = 0, eb = 0, ee = 0;
+  if (active) {
+    vb = vptr[v]; ve = vptr[v + 1];
+    eb = eptr[v]; ee = eptr[v + 1];
+  }
+  int jv[MV], ke[ME];
+  double wf[MV], wg[MV], cw[ME];
+#pragma unroll
+  for (int s = 0; s < MV; ++s) {
+    const int p = vb + lane + s * LPV;
+    jv[s] = p < ve ? vcol[p] : -1;
+    wf[s] = p < ve ? (double)wfg[2 * (size_t)p] : 0.0;
+    wg[s] = p < ve ? (double)wfg[2 * (size_t)p + 1] : 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < ME; ++s) {
+    const int p = eb + lane + s * LPV;
+    ke[s] = p < ee ? ecol[p] : -1;
+    cw[s] = p < ee ? (double)we[p] : 0.0;
+  }
+  double qv[MV][4], rv[ME][4];
+#pragma unroll
+  for (int s = 0; s < MV; ++s) load4(w, jv[s] >= 0 ? jv[s] : vv, qv[s]);
+#pragma unroll
+  for (int s = 0; s < ME; ++s) {
+    const double2* rp = reinterpret_cast<const double2*>(r + 4 * (size_t)(ke[s] >= 0 ? ke[s] : 0));
+    const double2 x = rp[0], y = rp[1];
+    rv[s][0] = x.x; rv[s][1] = x.y; rv[s][2] = y.x; rv[s][3] = y.y;
+  }
+  double q0[4], f0[4], g0[4];
+  load4(w, vv, q0);
+  euler_fg(q0, gm1, f0, g0);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < MV; ++s) {
+    if (jv[s] >= 0) {
+      double f[4], g[4];
+      euler_fg(qv[s], gm1, f, g);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] += wf[s] * (f[k] - f0[k]) + wg[s] * (g[k] - g0[k]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < ME; ++s)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += cw[s] * rv[s][k];
+  // tails (rare: stencils larger than the pipelined slots)
+  for (int p = vb + lane + MV * LPV; p < ve; p += LPV) {
+    const int j = vcol[p];
+    const double af = (double)wfg[2 * (size_t)p], ag = (double)wfg[2 * (size_t)p + 1];
+    double q[4], f[4], g[4];
+    load4(w, j, q);
+    euler_fg(q, gm1, f, g);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += af * (f[k] - f0[k]) + ag * (g[k] - g0[k]);
+  }
+  for (int p = eb + lane + ME * LPV; p < ee; p += LPV) {
+    const int k = ecol[p];
+    const double c = (double)we[p];
+    const double2* rp = reinterpret_cast<const double2*>(r + 4 * (size_t)k);
+    const double2 x = rp[0], y = rp[1];
+    acc[0] += c * x.x; acc[1] += c * x.y; acc[2] += c * y.x; acc[3] += c * y.y;
   }
 #pragma unroll
   for (int m = LPV / 2; m >= 1; m >>= 1) {

@@ -71,6 +71,8 @@ struct fdu_solver {
   DevBuf<double> geo, wfg, we, cO, hmin, flux, part;
   DevBuf<float> geo32, wfg32, we32;
   int cfl_blocks = 0;
+  int edge_variant = 0;    // 0: k_edge_flux, 1: k_edge_flux_lean
+  int vertex_variant = 0;  // 0: k_vertex (16 lanes, loops), 1-3: k_vertex_pipe with 16, 32, 8 lanes
 };
 
 namespace {
@@ -135,34 +137,69 @@ void fill_ghosts_t(fdu_solver* s, T* w, hipStream_t st) {
   launch_check();
 }
 
+constexpr int kEdgeVariants = 2;
+constexpr int kVertexVariants = 8;
+
+template <class T, class TG>
+void edge_flux_launch(fdu_solver* s, const T* w, const TG* geo, double* r, hipStream_t st) {
+  const Scheme S = scheme_of(s);
+  const dim3 grid(nblocks(s->ne_flux)), block(256);
+  if (s->edge_variant == 1)
+    hipLaunchKernelGGL((k_edge_flux_lean<T, TG>), grid, block, 0, st, w, s->sten.p, geo, r, (int)s->ne_flux, S);
+  else
+    hipLaunchKernelGGL((k_edge_flux<T, TG>), grid, block, 0, st, w, s->sten.p, geo, r, (int)s->ne_flux, S);
+}
+
 template <class T>
 void edge_flux_t(fdu_solver* s, const T* w, double* r, hipStream_t st) {
   if (s->ne_flux == 0) return;
-  const Scheme S = scheme_of(s);
   if (s->prec == FDU_F64)
-    hipLaunchKernelGGL((k_edge_flux<T, double>), dim3(nblocks(s->ne_flux)), dim3(256), 0, st, w, s->sten.p, s->geo.p,
-                       r, (int)s->ne_flux, S);
+    edge_flux_launch<T, double>(s, w, s->geo.p, r, st);
   else
-    hipLaunchKernelGGL((k_edge_flux<T, float>), dim3(nblocks(s->ne_flux)), dim3(256), 0, st, w, s->sten.p,
-                       s->geo32.p, r, (int)s->ne_flux, S);
+    edge_flux_launch<T, float>(s, w, s->geo32.p, r, st);
   launch_check();
 }
 
-constexpr int kLPV = 16;
+template <class T, class TW, int LPV, int MV, int ME>
+void vertex_pipe_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
+                        double a, double b, const double* dt, hipStream_t st) {
+  const unsigned nb = nblocks(s->nv_real * LPV);
+  hipLaunchKernelGGL((k_vertex_pipe<T, TW, LPV, MV, ME>), dim3(nb), dim3(256), 0, st, w, s->vptr.p, s->vcol.p, wfg,
+                     s->eptr.p, s->ecol.p, we, s->cO.p, s->flux.p, (int)s->nv_real, s->params.gamma - 1.0, mode, R,
+                     wn, out, a, b, dt);
+}
+
+template <class T, class TW, int LPV, bool NT>
+void vertex_loop_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
+                        double a, double b, const double* dt, hipStream_t st) {
+  const unsigned nb = nblocks(s->nv_real * LPV);
+  hipLaunchKernelGGL((k_vertex<T, TW, LPV, NT>), dim3(nb), dim3(256), 0, st, w, s->vptr.p, s->vcol.p, wfg, s->eptr.p,
+                     s->ecol.p, we, s->cO.p, s->flux.p, (int)s->nv_real, s->params.gamma - 1.0, mode, R, wn, out, a, b,
+                     dt);
+}
+
+template <class T, class TW>
+void vertex_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
+                   double a, double b, const double* dt, hipStream_t st) {
+  switch (s->vertex_variant) {
+    case 1: vertex_pipe_launch<T, TW, 16, 2, 3>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 2: vertex_pipe_launch<T, TW, 32, 1, 2>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 3: vertex_pipe_launch<T, TW, 8, 3, 6>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 4: vertex_loop_launch<T, TW, 8, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 5: vertex_loop_launch<T, TW, 4, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 6: vertex_loop_launch<T, TW, 16, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 7: vertex_loop_launch<T, TW, 8, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    default: vertex_loop_launch<T, TW, 16, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st);
+  }
+}
 
 template <class T>
 void vertex_t(fdu_solver* s, const T* w, int mode, T* R, const T* wn, T* out, double a, double b, const double* dt,
               hipStream_t st) {
-  const unsigned nb = nblocks(s->nv_real * kLPV);
-  const double gm1 = s->params.gamma - 1.0;
   if (s->prec == FDU_F64)
-    hipLaunchKernelGGL((k_vertex<T, double, kLPV>), dim3(nb), dim3(256), 0, st, w, s->vptr.p, s->vcol.p, s->wfg.p,
-                       s->eptr.p, s->ecol.p, s->we.p, s->cO.p, s->flux.p, (int)s->nv_real, gm1, mode, R, wn, out, a,
-                       b, dt);
+    vertex_launch<T, double>(s, w, s->wfg.p, s->we.p, mode, R, wn, out, a, b, dt, st);
   else
-    hipLaunchKernelGGL((k_vertex<T, float, kLPV>), dim3(nb), dim3(256), 0, st, w, s->vptr.p, s->vcol.p, s->wfg32.p,
-                       s->eptr.p, s->ecol.p, s->we32.p, s->cO.p, s->flux.p, (int)s->nv_real, gm1, mode, R, wn, out,
-                       a, b, dt);
+    vertex_launch<T, float>(s, w, s->wfg32.p, s->we32.p, mode, R, wn, out, a, b, dt, st);
   launch_check();
 }
 
@@ -679,6 +716,26 @@ fdu_status fdu_rk_step_vjp(fdu_solver* s, void* w_n, const void* wbar_np1, void*
   });
 }
 
+fdu_status fdu_set_variants(fdu_solver* s, int edge_variant, int vertex_variant) {
+  return guard([&] {
+    need(s != nullptr, "NULL solver");
+    need(edge_variant >= 0 && edge_variant < kEdgeVariants, "edge variant out of range");
+    need(vertex_variant >= 0 && vertex_variant < kVertexVariants, "vertex variant out of range");
+    s->edge_variant = edge_variant;
+    s->vertex_variant = vertex_variant;
+  });
+}
+
+fdu_status fdu_get_variants(const fdu_solver* s, int* edge_variant, int* vertex_variant, int* n_edge, int* n_vertex) {
+  return guard([&] {
+    need(s != nullptr, "NULL solver");
+    if (edge_variant) *edge_variant = s->edge_variant;
+    if (vertex_variant) *vertex_variant = s->vertex_variant;
+    if (n_edge) *n_edge = kEdgeVariants;
+    if (n_vertex) *n_vertex = kVertexVariants;
+  });
+}
+
 fdu_status fdu_kernel_times(fdu_solver* s, void* w, void* scratch, int reps, double* avg_ms, void* stream) {
   return guard([&] {
     ready(s);
@@ -716,6 +773,34 @@ fdu_status fdu_kernel_times(fdu_solver* s, void* w, void* scratch, int reps, dou
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+  });
+}
+
+fdu_status fdu_autotune(fdu_solver* s, void* w, void* scratch, int reps, double* times_ms, void* stream) {
+  return guard([&] {
+    ready(s);
+    need(w && scratch && times_ms && reps > 0, "invalid argument");
+    const int e0 = s->edge_variant, v0 = s->vertex_variant;
+    double best_e = 1e300, best_v = 1e300;
+    int be = e0, bv = v0;
+    for (int e = 0; e < kEdgeVariants; ++e) {
+      s->edge_variant = e;
+      double t[4];
+      fdu_status st = fdu_kernel_times(s, w, scratch, reps, t, stream);
+      if (st != FDU_OK) { s->edge_variant = e0; s->vertex_variant = v0; throw Error(st, fdu_last_error()); }
+      times_ms[e] = t[1];
+      if (t[1] < best_e) { best_e = t[1]; be = e; }
+    }
+    s->edge_variant = be;
+    for (int v = 0; v < kVertexVariants; ++v) {
+      s->vertex_variant = v;
+      double t[4];
+      fdu_status st = fdu_kernel_times(s, w, scratch, reps, t, stream);
+      if (st != FDU_OK) { s->edge_variant = e0; s->vertex_variant = v0; throw Error(st, fdu_last_error()); }
+      times_ms[kEdgeVariants + v] = t[2];
+      if (t[2] < best_v) { best_v = t[2]; bv = v; }
+    }
+    s->vertex_variant = bv;
   });
 }
 

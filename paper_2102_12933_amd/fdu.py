@@ -63,6 +63,9 @@ _SIGS = {
     "fdu_rk_step": (I32, [VP, VP, VP, D, VP, VP]),
     "fdu_kernel_times": (I32, [VP, VP, VP, I32, VP, VP]),
     "fdu_enable_adjoint": (I32, [VP]),
+    "fdu_set_variants": (I32, [VP, I32, I32]),
+    "fdu_get_variants": (I32, [VP, P(I32), P(I32), P(I32), P(I32)]),
+    "fdu_autotune": (I32, [VP, VP, VP, I32, VP, VP]),
     "fdu_residual_vjp": (I32, [VP, VP, VP, VP, VP]),
     "fdu_rk_stage_vjp": (I32, [VP, I32, VP, VP, VP, VP, D, VP]),
     "fdu_rk_step_vjp": (I32, [VP, VP, VP, VP, VP, VP, D, VP]),
@@ -273,6 +276,26 @@ class Solver:
             raise ValueError("scratch must hold four states")
         _call("fdu_rk_step_vjp", self.handle, self._state(w_n), self._state(wbar_np1), self._state(wbar_n),
               C.c_void_p(scratch.data_ptr()), self._dt(dt_dev), float(dt), _stream())
+
+    # -- kernel variants
+    def set_variants(self, edge: int, vertex: int):
+        _call("fdu_set_variants", self.handle, int(edge), int(vertex))
+
+    def variants(self):
+        e, v, ne, nv = (C.c_int() for _ in range(4))
+        _call("fdu_get_variants", self.handle, C.byref(e), C.byref(v), C.byref(ne), C.byref(nv))
+        return dict(edge=e.value, vertex=v.value, n_edge=ne.value, n_vertex=nv.value)
+
+    def autotune(self, w, reps: int = 10):
+        """Time every kernel variant on state w; keep the fastest.  Returns the times (ms)."""
+        info = self.variants()
+        n = info["n_edge"] + info["n_vertex"]
+        scratch = torch.empty(self.nv_total + 2, 4, dtype=self.dtype, device=w.device)
+        out = (C.c_double * n)()
+        _call("fdu_autotune", self.handle, self._state(w), C.c_void_p(scratch.data_ptr()), int(reps), out, _stream())
+        ch = self.variants()
+        return dict(edge_ms=list(out[:info["n_edge"]]), vertex_ms=list(out[info["n_edge"]:]),
+                    edge=ch["edge"], vertex=ch["vertex"])
 
     def kernel_times(self, w, reps: int = 20):
         """Mean kernel durations in ms: ghost fill, edge flux, vertex step, CFL."""

@@ -245,3 +245,22 @@ def batch_specs(n: int = 64, n_min: int = 65, n_max: int = 513, seed: int = 42,
     machs = rng.uniform(*mach_range, size=n)
     return [dict(N=int(Ns[i]), seed=mesh_seed0 + i, beta=float(betas[i]), mach=float(machs[i]))
             for i in range(n)]
+
+
+def vertex_areas(mesh) -> np.ndarray:
+    """Median-dual-like vertex areas: one third of the areas of the triangles
+    incident to each vertex ([nv] float64; ghost triangles count for their
+    vertices too, callers take the real rows)."""
+    t = mesh.tri.astype(np.int64)
+    p0 = mesh.xy[t[:, 0]]
+    d1 = mesh.xy[t[:, 1]] - p0
+    d2 = mesh.xy[t[:, 2]] - p0
+    if mesh.periodic:
+        L = np.asarray(mesh.box)
+        d1 = d1 - L * np.round(d1 / L)
+        d2 = d2 - L * np.round(d2 / L)
+    area = 0.5 * np.abs(d1[:, 0] * d2[:, 1] - d1[:, 1] * d2[:, 0])
+    A = np.zeros(mesh.nv)
+    for k in range(3):
+        np.add.at(A, t[:, k], area / 3.0)
+    return A

@@ -236,3 +236,34 @@ def test_full_size_sod_sampled():
     err1 = rel_err_per_component(st1[iperm[sample]], ref1)
     print("first stage rel err", err1)
     assert err1.max() <= 1e-14
+
+
+@pytest.mark.parametrize("edge,vertex", [(e, v) for e in range(2) for v in range(8)])
+def test_kernel_variants(vortex33_p5, sod24_p5, edge, vertex):
+    """Every kernel variant computes the same residual (to the parity bar)."""
+    for c in (vortex33_p5, sod24_p5):
+        c.s.set_variants(edge, vertex)
+        try:
+            err = _residual_err(c)
+            dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+            wn = c.w_dev()
+            out = torch.empty_like(wn)
+            c.s.rk_stage(1, wn, c.w_dev(), out, dt)
+            ref = c.o.rk3_stage(1, torch.from_numpy(c.w0), torch.from_numpy(c.w0), 1e-3).numpy()[c.perm]
+            nr = c.m.nv_real
+            err_st = rel_err_per_component(out.cpu().numpy()[:nr], ref[:nr])
+        finally:
+            c.s.set_variants(0, 0)
+        print(edge, vertex, err, err_st)
+        assert err.max() <= TOL and err_st.max() <= 1e-14
+
+
+def test_autotune_picks_a_variant(vortex33_p5):
+    c = vortex33_p5
+    res = c.s.autotune(c.w_dev(), reps=3)
+    info = c.s.variants()
+    assert len(res["edge_ms"]) == info["n_edge"] and len(res["vertex_ms"]) == info["n_vertex"]
+    assert res["edge"] == int(np.argmin(res["edge_ms"])) and res["vertex"] == int(np.argmin(res["vertex_ms"]))
+    err = _residual_err(c)
+    c.s.set_variants(0, 0)
+    assert err.max() <= TOL
