@@ -101,6 +101,125 @@ def cpu_baseline(mesh, w_input, budget_s=15.0, patch=48):
                        f"{el:.1f} s")
 
 
+def bench_batched(n_inst, steps, cfl, edge_variant, log):
+    """Batched vortex workload: n_inst instances (N ~ U{65..513}, strength ~ U[2,6],
+    Mach ~ U[0.3,0.8]), `steps` SSP-RK3 steps captured in one HIP graph, for each
+    schedule; the plain per-instance path is schedule 2 (every instance's own
+    kernels in turn) in the same kind of graph."""
+    import numpy as np
+    import torch
+    from paper_2102_12933_amd import fdu
+    from paper_2102_12933_amd.inputs import batch_specs, make_mesh, vortex_state
+    from paper_2102_12933_amd.tuning import autotune_batch
+
+    t0 = time.perf_counter()
+    specs = batch_specs(n=n_inst)
+    solvers, w0s = [], []
+    for i, sp in enumerate(specs):
+        m = make_mesh(sp["N"], L=10.0, periodic=True, seed=sp["seed"])
+        prep = fdu.Prep(m, deg=5, reorder=1)
+        perm = prep.arrays()["perm"]
+        s = fdu.Solver(prep, device=0)
+        s.set_variants(edge_variant, 0)
+        solvers.append(s)
+        w0s.append(torch.from_numpy(np.ascontiguousarray(vortex_state(m, beta=sp["beta"], mach=sp["mach"])[perm])).cuda())
+        if (i + 1) % 16 == 0:
+            log(f"batch: {i + 1}/{n_inst} instances prepared ({time.perf_counter() - t0:.0f} s)")
+    nv = sum(s.nv_real for s in solvers)
+    b = fdu.Batch(solvers)
+    ws = [w.clone() for w in w0s]
+    scr = [torch.empty(2 * s.nv_total, 4, dtype=torch.float64, device="cuda") for s in solvers]
+    b.set_states(ws, scr)
+    best, tune_ms = autotune_batch(b, cfl, use_cache=False)
+    log(f"batch autotune: best {best}; " + ", ".join(f"{k}: {v:.2f} ms" for k, v in tune_ms.items()))
+    side = torch.cuda.Stream()
+    res = {}
+    for label, cand in [("per_instance", (2, 4, 8, 16)), ("per_phase", (1, best[1], best[2], best[3]) if best[0] == 0 else (1, 4, 8, 16)),
+                        ("persistent", best if best[0] == 0 else (0, 4, 8, 16))]:
+        b.set_schedule(*cand)
+        for w, w0 in zip(ws, w0s):
+            w.copy_(w0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            b.capture(cfl, steps)
+            b.launch()                          # warm-up replay
+        side.synchronize()
+        for w, w0 in zip(ws, w0s):
+            w.copy_(w0)
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        with torch.cuda.stream(side):
+            b.launch()
+        side.synchronize()
+        el = time.perf_counter() - tt
+        err, dts = b.status()
+        ok = err == 0 and all(bool(torch.isfinite(w).all()) for w in ws)
+        res[label] = dict(schedule=list(cand), ms_per_step=round(el / steps * 1e3, 4),
+                          vertex_stage_per_s=nv * 3 * steps / el, wait_timeouts=err, finite=ok)
+        log(f"batch {label} {cand}: {el / steps * 1e3:.3f} ms/step, {nv * 3 * steps / el:.3e} vertex-stage/s")
+    return dict(instances=n_inst, vertices=int(nv), steps=steps, cfl=cfl, graph=True,
+                speedup_vs_per_instance=round(res["persistent"]["vertex_stage_per_s"] /
+                                              res["per_instance"]["vertex_stage_per_s"], 3),
+                schedules=res, autotune_ms={",".join(map(str, k)): round(v, 4) for k, v in tune_ms.items()})
+
+
+def bench_adjoint(N, nsteps, ckpt, log):
+    """Unrolled-gradient workload: vortex on an N^2 jittered periodic mesh, nsteps
+    SSP-RK3 steps at the t = 0 CFL-0.5 time step, checkpoints every ckpt steps,
+    gradient of sum_v A_v (p_v / rho_v^gamma - 1) with respect to the initial
+    state.  WENO eps = 1e-6 (differentiable weights)."""
+    import numpy as np
+    import torch
+    from paper_2102_12933_amd import fdu
+    from paper_2102_12933_amd.autograd import rk_unroll
+    from paper_2102_12933_amd.inputs import make_mesh, vertex_areas, vortex_state
+
+    m = make_mesh(N, L=10.0, periodic=True, seed=0)
+    prep = fdu.Prep(m, deg=5, reorder=1)
+    perm = prep.arrays()["perm"]
+    s = fdu.Solver(prep, device=0, weno_eps=1e-6)
+    s.enable_adjoint()
+    w0 = torch.from_numpy(np.ascontiguousarray(vortex_state(m, beta=5.0, mach=0.5)[perm])).cuda()
+    dt = float(s.cfl_dt(w0, 0.5).item())
+    A = torch.from_numpy(vertex_areas(m)[perm][:m.nv_real]).cuda()
+
+    def J(w):
+        wr = w[:m.nv_real]
+        rho = wr[:, 0]
+        p = 0.4 * (wr[:, 3] - 0.5 * (wr[:, 1] ** 2 + wr[:, 2] ** 2) / rho)
+        return torch.sum(A * (p / rho ** 1.4 - 1.0))
+
+    def fwd():
+        with torch.no_grad():
+            return J(rk_unroll(s, w0, nsteps, dt, ckpt))
+
+    def fwd_bwd():
+        x = w0.clone().requires_grad_(True)
+        val = J(rk_unroll(s, x, nsteps, dt, ckpt))
+        (g,) = torch.autograd.grad(val, x)
+        return g
+
+    fwd(); fwd_bwd()
+    torch.cuda.synchronize()
+    reps = 3
+    t = time.perf_counter()
+    for _ in range(reps):
+        fwd()
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - t) / reps
+    t = time.perf_counter()
+    for _ in range(reps):
+        g = fwd_bwd()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t) / reps
+    vs = m.nv_real * 3 * nsteps
+    log(f"adjoint {N}^2: forward {tf * 1e3:.1f} ms, forward+backward {tb * 1e3:.1f} ms")
+    return dict(workload=f"vortex {N}x{N} jittered periodic, {nsteps} SSP-RK3 steps, checkpoints every {ckpt}",
+                vertices=int(m.nv_real), forward_ms=round(tf * 1e3, 3), forward_backward_ms=round(tb * 1e3, 3),
+                ratio=round(tb / tf, 3), forward_vertex_stage_per_s=vs / tf, gradient_vertex_stage_per_s=vs / tb,
+                grad_finite=bool(torch.isfinite(g).all()))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +230,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=30)
     ap.add_argument("--cfl", type=float, default=SOD_CFL)
+    ap.add_argument("--batch-instances", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--adjoint-N", type=int, default=257)
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 512 MiB buffer 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -212,6 +336,10 @@ def main():
                      "edge_ms": [round(t, 5) for t in tune["edge_ms"]],
                      "vertex_ms": [round(t, 5) for t in tune["vertex_ms"]]},
     }
+    if not args.no_batch:
+        out["batched"] = bench_batched(args.batch_instances, args.batch_steps, 0.5, tune["edge"], log)
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(args.adjoint_N, 20, 5, log)
     if not args.no_cpu_baseline:
         w_in = np.empty((mesh.nv, 4))
         w_in[perm] = w3.cpu().numpy()

@@ -233,6 +233,40 @@ fdu_status fdu_rk_step_vjp(fdu_solver* s, void* w_n, const void* wbar_np1, void*
  * The timed work equals the work of the corresponding compute calls. */
 fdu_status fdu_kernel_times(fdu_solver* s, void* w, void* scratch, int reps, double* avg_ms, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many FP64 instances (finalized solvers on one device with equal
+ * scheme parameters and edge variant) advanced together.
+ * fdu_batch_create: builds the tile tables (set-up, synchronous).
+ * fdu_batch_set_states: per instance, w[i] (device [nv_total_i][4] double,
+ *   in/out) and scratch[i] (device, two states); pointers are captured, so a
+ *   later call re-binds them (and drops a captured graph).
+ * fdu_batch_set_schedule: 0 = one persistent launch per stage for all
+ *   instances (tiles in ticket order, per-instance completion counters,
+ *   bounded dependency waits); 1 = one launch per phase (ghost, edge, vertex)
+ *   for all instances; 2 = every instance's own stage kernels in turn.  Tile
+ *   shape: edges_per_thread (edge tile = 256 x that), vertex_passes and
+ *   lanes_per_vertex (8 or 16; vertex tile = passes x 256 / lanes).
+ * fdu_batch_step: one SSP-RK3 step of every instance with its own dt =
+ *   cfl * min hmin/(|u|+c) (computed on the device), asynchronous on stream.
+ * fdu_batch_capture: records nsteps steps on stream (not the default stream)
+ *   into a HIP graph owned by the batch; fdu_batch_launch replays it.
+ * fdu_batch_status: synchronizes the device; returns the dependency-wait
+ *   timeout flag (0 = none) and copies the last per-instance dt to the host.
+ * fdu_batch_info: current schedule, tile count, fused grid size, tile shape.
+ */
+typedef struct fdu_batch fdu_batch;
+fdu_status fdu_batch_create(fdu_batch** out, fdu_solver* const* inst, int n);
+void fdu_batch_destroy(fdu_batch* b);
+fdu_status fdu_batch_set_states(fdu_batch* b, void* const* w, void* const* scratch);
+fdu_status fdu_batch_set_schedule(fdu_batch* b, int schedule, int edges_per_thread, int vertex_passes,
+                                  int lanes_per_vertex);
+fdu_status fdu_batch_step(fdu_batch* b, double cfl, void* stream);
+fdu_status fdu_batch_capture(fdu_batch* b, double cfl, int nsteps, void* stream);
+fdu_status fdu_batch_launch(fdu_batch* b, void* stream);
+fdu_status fdu_batch_status(fdu_batch* b, int* wait_timeouts, double* dt_host);
+fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, int* grid, int* edges_per_thread,
+                          int* vertex_passes, int* lanes_per_vertex);
+
 /* Kernel variants and autotuning.  Every variant computes the same residual
  * (the parity tests run each one); they differ in schedule and register use:
  *   edge:   0 = coefficient-form WENO, IEEE divisions; 1 = divided-difference

@@ -1,0 +1,184 @@
+// Many mesh instances advanced together: one persistent launch per Runge-Kutta
+// stage covers every instance's ghost fill, edge fluxes and vertex step.
+//
+// Work is cut into tiles (ghost tiles, edge tiles, vertex tiles) laid out
+// phase-major over instances; workgroups take tiles in ticket order from one
+// counter.  An edge tile of instance i waits until i's ghost tiles are done, a
+// vertex tile until i's edge tiles are done (per-instance completion
+// counters, release/acquire at agent scope).  A tile only waits on tiles with
+// smaller tickets, which were taken by workgroups already running, so the
+// schedule needs no co-residency.  Every wait is bounded: on timeout an error
+// flag is set and the tile proceeds, so every wave always reaches its exit.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace fdu {
+
+struct BatchInst {
+  const int* sten;
+  const double* geo;
+  const int* vptr;
+  const int* vcol;
+  const double* wfg;
+  const int* eptr;
+  const int* ecol;
+  const double* we;
+  const double* cO;
+  const double* hmin;
+  const int* gsrc;
+  const signed char* grefl;
+  double* flux;
+  double* w;    // state (in/out)
+  double* w1;   // stage buffers
+  double* w2;
+  int nv_real, nv_total, ne, ng;
+};
+
+constexpr unsigned kWaitLimit = 1u << 22;
+
+__device__ __forceinline__ void wait_count(unsigned* c, unsigned target, int* err) {
+  if (threadIdx.x == 0) {
+    unsigned it = 0;
+    while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++it > kWaitLimit) {
+        atomicOr(err, 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void signal_count(unsigned* c) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// largest j in [0, m) with tb[j] <= t (tb non-decreasing, tb[0] = 0)
+__device__ __forceinline__ int find_slot(const int* __restrict__ tb, int m, int t) {
+  int lo = 0, hi = m - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tb[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct BatchTiling {
+  int ept;   // edges per thread in an edge tile (tile = 256 * ept edges)
+  int vp;    // vertex passes per tile (tile = vp * 256 / LPV vertices)
+};
+
+__device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// phase < 0: fused schedule with dynamic tickets and dependency waits;
+// phase 0/1/2: only that phase's tiles, one per block (no waits).
+template <int EV, int LPV>
+__global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict__ inst, int n,
+                                                     const int* __restrict__ tb, int total, unsigned* ctr, Scheme S,
+                                                     int k, double a, double b, const double* __restrict__ dt,
+                                                     int* err, BatchTiling tl, int phase) {
+  __shared__ int sh;
+  for (int iter = 0;; ++iter) {
+    int t;
+    if (phase < 0) {
+      __syncthreads();
+      if (threadIdx.x == 0) sh = (int)atomicAdd(&ctr[0], 1u);
+      __syncthreads();
+      t = sh;
+    } else {
+      if (iter > 0) return;
+      t = tb[phase * n] + blockIdx.x;
+      if (t >= tb[(phase + 1) * n]) return;
+    }
+    if (t >= total) return;
+    const int j = find_slot(tb, 3 * n, t);
+    const int p = j / n, i = j - p * n, local = t - tb[j];
+    const BatchInst& I = inst[i];
+    double* wprev = k == 0 ? I.w : (k == 1 ? I.w1 : I.w2);
+    double* wout = k == 0 ? I.w1 : (k == 1 ? I.w2 : I.w);
+    if (p == 0) {
+      const int g = local * 256 + threadIdx.x;
+      if (g < I.ng) {
+        double q[4];
+        load4(wprev, I.gsrc[g], q);
+        const int f = I.grefl[g];
+        if (f & 1) q[1] = -q[1];
+        if (f & 2) q[2] = -q[2];
+        store4(wprev, I.nv_real + g, q);
+      }
+      if (phase < 0) signal_count(&ctr[1 + i]);
+    } else if (p == 1) {
+      if (phase < 0 && I.ng > 0) wait_count(&ctr[1 + i], (unsigned)ceil_div(I.ng, 256), err);
+      for (int q = 0; q < tl.ept; ++q) {
+        const int e = (local * tl.ept + q) * 256 + threadIdx.x;
+        if (e < I.ne) {
+          if (EV == 1)
+            edge_lean_item<double, double>(wprev, I.sten, I.geo, I.flux, e, S);
+          else
+            edge_item<double, double>(wprev, I.sten, I.geo, I.flux, e, S);
+        }
+      }
+      if (phase < 0) signal_count(&ctr[1 + n + i]);
+    } else {
+      if (phase < 0) wait_count(&ctr[1 + n + i], (unsigned)ceil_div(I.ne, 256 * tl.ept), err);
+      for (int q = 0; q < tl.vp; ++q) {
+        const int tt = (local * tl.vp + q) * 256 + threadIdx.x;
+        const int v = tt / LPV;
+        vertex_item<double, double, LPV, false>(wprev, I.vptr, I.vcol, I.wfg, I.eptr, I.ecol, I.we, I.cO, I.flux,
+                                                I.nv_real, S.gm1, 1, nullptr, I.w, wout, a, b, dt + i, v,
+                                                tt % LPV);
+      }
+    }
+  }
+}
+
+// Per-instance CFL: block minima of hmin_v / (|u_v| + c_v) over 256-vertex
+// tiles, combined per instance with an integer atomicMin on the bit patterns
+// (positive doubles order like their bits, so the result is exact and
+// independent of the order).
+__global__ void __launch_bounds__(256) k_batch_cfl(const BatchInst* __restrict__ inst, int n,
+                                                   const int* __restrict__ tbc, int total, double gamma,
+                                                   unsigned long long* dtbits) {
+  __shared__ double sm[256];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_slot(tbc, n, t);
+    const BatchInst& I = inst[i];
+    const int v = (t - tbc[i]) * 256 + threadIdx.x;
+    double best = 1e300;
+    if (v < I.nv_real) {
+      double q[4];
+      load4(I.w, v, q);
+      const double ir = 1.0 / q[0];
+      const double u = q[1] * ir, vv = q[2] * ir;
+      const double p = (gamma - 1.0) * (q[3] - 0.5 * (q[1] * u + q[2] * vv));
+      best = I.hmin[v] / (sqrt(u * u + vv * vv) + sqrt(gamma * p * ir));
+    }
+    sm[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMin(&dtbits[i], (unsigned long long)__double_as_longlong(sm[0]));
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_batch_dt(const unsigned long long* __restrict__ dtbits, int n, double cfl,
+                                                  double* __restrict__ dt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dt[i] = cfl * __longlong_as_double((long long)dtbits[i]);
+}
+
+// Zero the stage counters; optionally reset the CFL minima to +inf.
+__global__ void __launch_bounds__(256) k_batch_reset(unsigned* ctr, int nctr, unsigned long long* dtbits, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nctr) ctr[i] = 0u;
+  if (dtbits != nullptr && i < n) dtbits[i] = 0x7FF0000000000000ull;
+}
+
+}  // namespace fdu

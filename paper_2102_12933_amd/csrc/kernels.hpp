@@ -365,11 +365,9 @@ __global__ void __launch_bounds__(256) k_fill_ghosts(T* __restrict__ w, int nrea
 }
 
 template <class T, class TG>
-__global__ void __launch_bounds__(256) k_edge_flux(const T* __restrict__ w, const int* __restrict__ sten,
-                                                   const TG* __restrict__ geo, double* __restrict__ r, int ne,
-                                                   Scheme S) {
-  const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
+__device__ __forceinline__ void edge_item(const T* __restrict__ w, const int* __restrict__ sten,
+                                          const TG* __restrict__ geo, double* __restrict__ r, int e,
+                                          const Scheme& S) {
   int id[6];
   {
     const int2* sp = reinterpret_cast<const int2*>(sten + 6 * (size_t)e);
@@ -389,6 +387,14 @@ __global__ void __launch_bounds__(256) k_edge_flux(const T* __restrict__ w, cons
   rp[1] = make_double2(out[2], out[3]);
 }
 
+template <class T, class TG>
+__global__ void __launch_bounds__(256) k_edge_flux(const T* __restrict__ w, const int* __restrict__ sten,
+                                                   const TG* __restrict__ geo, double* __restrict__ r, int ne,
+                                                   Scheme S) {
+  const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (e < ne) edge_item<T, TG>(w, sten, geo, r, e, S);
+}
+
 // Vertex step.  LPV lanes cooperate on one vertex: each accumulates a strided
 // share of the vertex terms wf (f_j - f_O) + wg (g_j - g_O) and of the edge
 // terms we r_k; a butterfly over the LPV lanes reduces them, no atomics.
@@ -403,16 +409,16 @@ __device__ __forceinline__ X ldstream(const X* p) {
     return *p;
 }
 
-template <class T, class TW, int LPV, bool NT = false>
-__global__ void __launch_bounds__(256) k_vertex(const T* __restrict__ w, const int* __restrict__ vptr,
-                                                const int* __restrict__ vcol, const TW* __restrict__ wfg,
-                                                const int* __restrict__ eptr, const int* __restrict__ ecol,
-                                                const TW* __restrict__ we, const double* __restrict__ cO,
-                                                const double* __restrict__ r, int nreal, double gm1, int mode,
-                                                T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
-                                                double a, double b, const double* __restrict__ dt_dev) {
-  const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const int v = t / LPV, lane = t % LPV;
+// One vertex of the vertex step, computed by the LPV lanes (lane = 0..LPV-1)
+// of its group; all LPV lanes must call it (butterfly reduction).
+template <class T, class TW, int LPV, bool NT>
+__device__ __forceinline__ void vertex_item(const T* __restrict__ w, const int* __restrict__ vptr,
+                                            const int* __restrict__ vcol, const TW* __restrict__ wfg,
+                                            const int* __restrict__ eptr, const int* __restrict__ ecol,
+                                            const TW* __restrict__ we, const double* __restrict__ cO,
+                                            const double* __restrict__ r, int nreal, double gm1, int mode,
+                                            T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
+                                            double a, double b, const double* __restrict__ dt_dev, int v, int lane) {
   const bool active = v < nreal;
   const int vv = active ? v : 0;
   double q0[4], f0[4], g0[4];
@@ -460,6 +466,19 @@ __global__ void __launch_bounds__(256) k_vertex(const T* __restrict__ w, const i
     for (int k = 0; k < 4; ++k) o[k] = a * n[k] + b * (q0[k] + dt * res[k]);
     store4(out, v, o);
   }
+}
+
+template <class T, class TW, int LPV, bool NT = false>
+__global__ void __launch_bounds__(256) k_vertex(const T* __restrict__ w, const int* __restrict__ vptr,
+                                                const int* __restrict__ vcol, const TW* __restrict__ wfg,
+                                                const int* __restrict__ eptr, const int* __restrict__ ecol,
+                                                const TW* __restrict__ we, const double* __restrict__ cO,
+                                                const double* __restrict__ r, int nreal, double gm1, int mode,
+                                                T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
+                                                double a, double b, const double* __restrict__ dt_dev) {
+  const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  vertex_item<T, TW, LPV, NT>(w, vptr, vcol, wfg, eptr, ecol, we, cO, r, nreal, gm1, mode, R, wn, out, a, b, dt_dev,
+                              t / LPV, t % LPV);
 }
 
 // ----------------------------------------------------------------------------
@@ -516,11 +535,9 @@ __device__ __forceinline__ double weno_dd_eval(const WenoDD& G, const double u[5
 // Edge flux, register-lean variant: one side's WENO geometry live at a time,
 // divided-difference interpolants, refined reciprocals.
 template <class T, class TG>
-__global__ void __launch_bounds__(256) k_edge_flux_lean(const T* __restrict__ w, const int* __restrict__ sten,
-                                                        const TG* __restrict__ geo, double* __restrict__ r, int ne,
-                                                        Scheme S) {
-  const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
+__device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const int* __restrict__ sten,
+                                               const TG* __restrict__ geo, double* __restrict__ r, int e,
+                                               const Scheme& S) {
   int id[6];
   {
     const int2* sp = reinterpret_cast<const int2*>(sten + 6 * (size_t)e);
@@ -579,6 +596,14 @@ __global__ void __launch_bounds__(256) k_edge_flux_lean(const T* __restrict__ w,
   double2* rp = reinterpret_cast<double2*>(r + 4 * (size_t)e);
   rp[0] = make_double2(out[0], out[1]);
   rp[1] = make_double2(out[2], out[3]);
+}
+
+template <class T, class TG>
+__global__ void __launch_bounds__(256) k_edge_flux_lean(const T* __restrict__ w, const int* __restrict__ sten,
+                                                        const TG* __restrict__ geo, double* __restrict__ r, int ne,
+                                                        Scheme S) {
+  const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (e < ne) edge_lean_item<T, TG>(w, sten, geo, r, e, S);
 }
 
 // Vertex step, software-pipelined: every lane first loads the ids and weights

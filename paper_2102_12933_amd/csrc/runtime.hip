@@ -4,12 +4,14 @@
 
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "fdu_internal.h"
 #include "kernels.hpp"
 #include "adjoint.hpp"
+#include "batch.hpp"
 
 namespace fdu {
 
@@ -389,6 +391,118 @@ void rk_step_vjp_t(fdu_solver* s, T* wn, const T* wbar_np1, T* wbar_n, T* scratc
 
 }  // namespace
 
+struct fdu_batch {
+  int device = 0;
+  int n = 0;
+  std::vector<fdu_solver*> inst;
+  Scheme S{};
+  int schedule = 0;     // 0 fused persistent, 1 one launch per phase, 2 per-instance kernels
+  BatchTiling tl{4, 8};
+  int lpv = 16;         // lanes per vertex in vertex tiles (16 or 8)
+  int grid = 0;         // blocks of the fused launch
+  int total = 0, ctiles = 0;
+  std::vector<int32_t> h_tb;
+  DevBuf<BatchInst> dinst;
+  DevBuf<int32_t> tb, tbc, err;
+  DevBuf<uint32_t> ctr;
+  DevBuf<unsigned long long> dtbits;
+  DevBuf<double> dt;
+  std::vector<BatchInst> h_inst;
+  bool have_states = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~fdu_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+namespace {
+
+void batch_tiles(fdu_batch* b) {
+  const int n = b->n;
+  const int per_v = b->tl.vp * (256 / b->lpv);
+  b->h_tb.assign(3 * n + 1, 0);
+  int acc = 0;
+  for (int p = 0; p < 3; ++p)
+    for (int i = 0; i < n; ++i) {
+      const fdu_solver* s = b->inst[i];
+      b->h_tb[p * n + i] = acc;
+      const int nt = p == 0 ? (int)((s->ng + 255) / 256)
+                   : p == 1 ? (int)((s->ne_flux + 256 * b->tl.ept - 1) / (256 * b->tl.ept))
+                            : (int)((s->nv_real + per_v - 1) / per_v);
+      acc += nt;
+    }
+  b->h_tb[3 * n] = acc;
+  b->total = acc;
+  b->tb.upload(b->h_tb.data(), b->h_tb.size());
+  std::vector<int32_t> tbc(n + 1, 0);
+  for (int i = 0; i < n; ++i) tbc[i + 1] = tbc[i] + (int)((b->inst[i]->nv_real + 255) / 256);
+  b->ctiles = tbc[n];
+  b->tbc.upload(tbc.data(), tbc.size());
+  int cus = 0, per_cu = 0;
+  FDU_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+  if (b->lpv == 8)
+    FDU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_stage<1, 8>, 256, 0));
+  else
+    FDU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_stage<1, 16>, 256, 0));
+  b->grid = std::max(1, std::min(b->total, cus * std::max(1, per_cu)));
+}
+
+template <int EV, int LPV>
+void batch_stage_launch(fdu_batch* b, int k, hipStream_t st, int phase, unsigned grid) {
+  hipLaunchKernelGGL((k_batch_stage<EV, LPV>), dim3(grid), dim3(256), 0, st, b->dinst.p, b->n, b->tb.p, b->total,
+                     b->ctr.p, b->S, k, kRK[k][0], kRK[k][1], b->dt.p, b->err.p, b->tl, phase);
+}
+
+void batch_stage(fdu_batch* b, int k, hipStream_t st) {
+  const int ev = b->inst[0]->edge_variant == 1 ? 1 : 0;
+  auto launch = [&](int phase, unsigned grid) {
+    if (ev == 1 && b->lpv == 8) batch_stage_launch<1, 8>(b, k, st, phase, grid);
+    else if (ev == 1) batch_stage_launch<1, 16>(b, k, st, phase, grid);
+    else if (b->lpv == 8) batch_stage_launch<0, 8>(b, k, st, phase, grid);
+    else batch_stage_launch<0, 16>(b, k, st, phase, grid);
+  };
+  if (b->schedule == 0) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(nblocks(1 + 2 * b->n)), dim3(256), 0, st, b->ctr.p, 1 + 2 * b->n,
+                       (unsigned long long*)nullptr, 0);
+    launch(-1, (unsigned)b->grid);
+  } else {
+    for (int p = 0; p < 3; ++p) {
+      const int ntiles = b->h_tb[(p + 1) * b->n] - b->h_tb[p * b->n];
+      if (ntiles > 0) launch(p, (unsigned)ntiles);
+    }
+  }
+  launch_check();
+}
+
+void batch_cfl(fdu_batch* b, double cfl, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(nblocks(b->n)), dim3(256), 0, st, b->ctr.p, 0, b->dtbits.p, b->n);
+  hipLaunchKernelGGL(k_batch_cfl, dim3(std::min(b->ctiles, 4096)), dim3(256), 0, st, b->dinst.p, b->n, b->tbc.p,
+                     b->ctiles, b->S.gamma, b->dtbits.p);
+  hipLaunchKernelGGL(k_batch_dt, dim3(nblocks(b->n)), dim3(256), 0, st, b->dtbits.p, b->n, cfl, b->dt.p);
+  launch_check();
+}
+
+void batch_step(fdu_batch* b, double cfl, hipStream_t st) {
+  if (!b->have_states) throw Error(FDU_ERR_STATE, "set the instance states first (fdu_batch_set_states)");
+  batch_cfl(b, cfl, st);
+  if (b->schedule == 2) {
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < b->n; ++i) {
+        fdu_solver* s = b->inst[i];
+        const BatchInst& I = b->h_inst[i];
+        double* wprev = k == 0 ? I.w : (k == 1 ? I.w1 : I.w2);
+        double* wout = k == 0 ? I.w1 : (k == 1 ? I.w2 : I.w);
+        rk_stage_t<double>(s, k, I.w, wprev, wout, b->dt.p + i, st);
+      }
+    return;
+  }
+  for (int k = 0; k < 3; ++k) batch_stage(b, k, st);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* fdu_last_error(void) { return g_last_error.c_str(); }
@@ -733,6 +847,151 @@ fdu_status fdu_get_variants(const fdu_solver* s, int* edge_variant, int* vertex_
     if (vertex_variant) *vertex_variant = s->vertex_variant;
     if (n_edge) *n_edge = kEdgeVariants;
     if (n_vertex) *n_vertex = kVertexVariants;
+  });
+}
+
+fdu_status fdu_batch_create(fdu_batch** out, fdu_solver* const* inst, int n) {
+  return guard([&] {
+    need(out && inst && n > 0, "invalid argument");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+      ready(inst[i]);
+      need(inst[i]->prec == FDU_F64, "batched instances must be FP64");
+      need(inst[i]->device == inst[0]->device, "batched instances must share a device");
+      need(std::memcmp(&inst[i]->params, &inst[0]->params, sizeof(fdu_params)) == 0,
+           "batched instances must share scheme parameters");
+      need(inst[i]->edge_variant == inst[0]->edge_variant, "batched instances must share the edge variant");
+    }
+    DeviceGuard dg(inst[0]->device);
+    std::unique_ptr<fdu_batch> b(new fdu_batch());
+    b->device = inst[0]->device;
+    b->n = n;
+    b->inst.assign(inst, inst + n);
+    b->S = scheme_of(inst[0]);
+    b->ctr.alloc(1 + 2 * n);
+    b->dtbits.alloc(n);
+    b->dt.alloc(n);
+    b->err.alloc(1);
+    int zero = 0;
+    FDU_HIP(hipMemcpy(b->err.p, &zero, sizeof(int), hipMemcpyHostToDevice));
+    batch_tiles(b.get());
+    *out = b.release();
+  });
+}
+
+void fdu_batch_destroy(fdu_batch* b) {
+  if (!b) return;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(b->device);
+  delete b;
+  (void)hipSetDevice(prev);
+}
+
+fdu_status fdu_batch_set_states(fdu_batch* b, void* const* w, void* const* scratch) {
+  return guard([&] {
+    need(b && w && scratch, "NULL argument");
+    DeviceGuard dg(b->device);
+    b->h_inst.resize(b->n);
+    for (int i = 0; i < b->n; ++i) {
+      need(w[i] && scratch[i], "NULL state or scratch");
+      fdu_solver* s = b->inst[i];
+      BatchInst& I = b->h_inst[i];
+      I.sten = s->sten.p; I.geo = s->geo.p; I.vptr = s->vptr.p; I.vcol = s->vcol.p; I.wfg = s->wfg.p;
+      I.eptr = s->eptr.p; I.ecol = s->ecol.p; I.we = s->we.p; I.cO = s->cO.p; I.hmin = s->hmin.p;
+      I.gsrc = s->gsrc.p; I.grefl = reinterpret_cast<const signed char*>(s->grefl.p); I.flux = s->flux.p;
+      I.w = (double*)w[i];
+      I.w1 = (double*)scratch[i];
+      I.w2 = (double*)scratch[i] + 4 * s->nv_total;
+      I.nv_real = (int)s->nv_real; I.nv_total = (int)s->nv_total; I.ne = (int)s->ne_flux; I.ng = (int)s->ng;
+    }
+    b->dinst.upload(b->h_inst.data(), b->h_inst.size());
+    b->have_states = true;
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  });
+}
+
+fdu_status fdu_batch_set_schedule(fdu_batch* b, int schedule, int edges_per_thread, int vertex_passes,
+                                  int lanes_per_vertex) {
+  return guard([&] {
+    need(b != nullptr, "NULL batch");
+    need(schedule >= 0 && schedule <= 2, "schedule must be 0, 1 or 2");
+    need(edges_per_thread >= 1 && edges_per_thread <= 64, "edges_per_thread out of range");
+    need(vertex_passes >= 1 && vertex_passes <= 64, "vertex_passes out of range");
+    need(lanes_per_vertex == 8 || lanes_per_vertex == 16, "lanes_per_vertex must be 8 or 16");
+    DeviceGuard dg(b->device);
+    b->schedule = schedule;
+    b->tl.ept = edges_per_thread;
+    b->tl.vp = vertex_passes;
+    b->lpv = lanes_per_vertex;
+    batch_tiles(b);
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  });
+}
+
+fdu_status fdu_batch_step(fdu_batch* b, double cfl, void* stream) {
+  return guard([&] {
+    need(b != nullptr, "NULL batch");
+    need(cfl > 0 && std::isfinite(cfl), "cfl must be positive");
+    DeviceGuard dg(b->device);
+    batch_step(b, cfl, (hipStream_t)stream);
+  });
+}
+
+fdu_status fdu_batch_capture(fdu_batch* b, double cfl, int nsteps, void* stream) {
+  return guard([&] {
+    need(b != nullptr && stream != nullptr, "a non-default stream is required for capture");
+    need(nsteps > 0 && cfl > 0 && std::isfinite(cfl), "invalid steps or cfl");
+    if (!b->have_states) throw Error(FDU_ERR_STATE, "set the instance states first (fdu_batch_set_states)");
+    DeviceGuard dg(b->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    FDU_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int i = 0; i < nsteps; ++i) batch_step(b, cfl, st);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(st, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    FDU_HIP(hipStreamEndCapture(st, &b->graph));
+    FDU_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  });
+}
+
+fdu_status fdu_batch_launch(fdu_batch* b, void* stream) {
+  return guard([&] {
+    need(b != nullptr, "NULL batch");
+    if (!b->exec) throw Error(FDU_ERR_STATE, "nothing captured (fdu_batch_capture)");
+    DeviceGuard dg(b->device);
+    FDU_HIP(hipGraphLaunch(b->exec, (hipStream_t)stream));
+  });
+}
+
+fdu_status fdu_batch_status(fdu_batch* b, int* wait_timeouts, double* dt_host) {
+  return guard([&] {
+    need(b != nullptr, "NULL batch");
+    DeviceGuard dg(b->device);
+    FDU_HIP(hipDeviceSynchronize());
+    if (wait_timeouts) FDU_HIP(hipMemcpy(wait_timeouts, b->err.p, sizeof(int), hipMemcpyDeviceToHost));
+    if (dt_host) FDU_HIP(hipMemcpy(dt_host, b->dt.p, b->n * sizeof(double), hipMemcpyDeviceToHost));
+  });
+}
+
+fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, int* grid, int* edges_per_thread,
+                          int* vertex_passes, int* lanes_per_vertex) {
+  return guard([&] {
+    need(b != nullptr, "NULL batch");
+    if (schedule) *schedule = b->schedule;
+    if (total_tiles) *total_tiles = b->total;
+    if (grid) *grid = b->grid;
+    if (edges_per_thread) *edges_per_thread = b->tl.ept;
+    if (vertex_passes) *vertex_passes = b->tl.vp;
+    if (lanes_per_vertex) *lanes_per_vertex = b->lpv;
   });
 }
 

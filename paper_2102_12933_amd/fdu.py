@@ -66,6 +66,15 @@ _SIGS = {
     "fdu_set_variants": (I32, [VP, I32, I32]),
     "fdu_get_variants": (I32, [VP, P(I32), P(I32), P(I32), P(I32)]),
     "fdu_autotune": (I32, [VP, VP, VP, I32, VP, VP]),
+    "fdu_batch_create": (I32, [P(VP), VP, I32]),
+    "fdu_batch_destroy": (None, [VP]),
+    "fdu_batch_set_states": (I32, [VP, VP, VP]),
+    "fdu_batch_set_schedule": (I32, [VP, I32, I32, I32, I32]),
+    "fdu_batch_step": (I32, [VP, D, VP]),
+    "fdu_batch_capture": (I32, [VP, D, I32, VP]),
+    "fdu_batch_launch": (I32, [VP, VP]),
+    "fdu_batch_status": (I32, [VP, P(I32), VP]),
+    "fdu_batch_info": (I32, [VP, P(I32), P(I32), P(I32), P(I32), P(I32), P(I32)]),
     "fdu_residual_vjp": (I32, [VP, VP, VP, VP, VP]),
     "fdu_rk_stage_vjp": (I32, [VP, I32, VP, VP, VP, VP, D, VP]),
     "fdu_rk_step_vjp": (I32, [VP, VP, VP, VP, VP, VP, D, VP]),
@@ -308,6 +317,64 @@ class Solver:
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.fdu_destroy(self.handle)
+            self.handle = None
+
+
+class Batch:
+    """Several FP64 solvers advanced together (one persistent launch per stage,
+    or per phase, or per instance), optionally captured in a HIP graph."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        arr = (C.c_void_p * len(self.solvers))(*[s.handle.value for s in self.solvers])
+        h = C.c_void_p()
+        _call("fdu_batch_create", C.byref(h), arr, len(self.solvers))
+        self.handle = h
+        self._keep = None
+
+    def set_states(self, states, scratches):
+        for s, w, sc in zip(self.solvers, states, scratches):
+            s._state(w)
+            if not (sc.is_cuda and sc.dtype == torch.float64 and sc.is_contiguous() and sc.numel() >= 8 * s.nv_total):
+                raise ValueError("each scratch must hold two states")
+        n = len(self.solvers)
+        ws = (C.c_void_p * n)(*[w.data_ptr() for w in states])
+        ss = (C.c_void_p * n)(*[sc.data_ptr() for sc in scratches])
+        _call("fdu_batch_set_states", self.handle, ws, ss)
+        self._keep = (list(states), list(scratches))
+
+    def set_schedule(self, schedule: int, edges_per_thread: int = 4, vertex_passes: int = 8,
+                     lanes_per_vertex: int = 16):
+        _call("fdu_batch_set_schedule", self.handle, int(schedule), int(edges_per_thread), int(vertex_passes),
+              int(lanes_per_vertex))
+
+    def step(self, cfl: float):
+        _call("fdu_batch_step", self.handle, float(cfl), _stream())
+
+    def capture(self, cfl: float, nsteps: int):
+        st = torch.cuda.current_stream().cuda_stream
+        if not st:
+            raise ValueError("capture needs a non-default stream (use torch.cuda.stream(...))")
+        _call("fdu_batch_capture", self.handle, float(cfl), int(nsteps), C.c_void_p(st))
+
+    def launch(self):
+        _call("fdu_batch_launch", self.handle, _stream())
+
+    def status(self):
+        e = C.c_int()
+        dt = np.zeros(len(self.solvers))
+        _call("fdu_batch_status", self.handle, C.byref(e), dt.ctypes.data_as(C.c_void_p))
+        return e.value, dt
+
+    def info(self):
+        vals = [C.c_int() for _ in range(6)]
+        _call("fdu_batch_info", self.handle, *[C.byref(v) for v in vals])
+        keys = ["schedule", "total_tiles", "grid", "edges_per_thread", "vertex_passes", "lanes_per_vertex"]
+        return {k: v.value for k, v in zip(keys, vals)}
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fdu_batch_destroy(self.handle)
             self.handle = None
 
 
