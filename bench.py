@@ -101,7 +101,7 @@ def cpu_baseline(mesh, w_input, budget_s=15.0, patch=48):
                        f"{el:.1f} s")
 
 
-def bench_batched(n_inst, steps, cfl, edge_variant, log):
+def bench_batched(n_inst, steps, cfl, edge_variant, vertex_variant, log):
     """Batched vortex workload: n_inst instances (N ~ U{65..513}, strength ~ U[2,6],
     Mach ~ U[0.3,0.8]), `steps` SSP-RK3 steps captured in one HIP graph, for each
     schedule; the plain per-instance path is schedule 2 (every instance's own
@@ -120,7 +120,7 @@ def bench_batched(n_inst, steps, cfl, edge_variant, log):
         prep = fdu.Prep(m, deg=5, reorder=1)
         perm = prep.arrays()["perm"]
         s = fdu.Solver(prep, device=0)
-        s.set_variants(edge_variant, 0)
+        s.set_variants(edge_variant, vertex_variant)       # used by the per-instance schedule
         solvers.append(s)
         w0s.append(torch.from_numpy(np.ascontiguousarray(vortex_state(m, beta=sp["beta"], mach=sp["mach"])[perm])).cuda())
         if (i + 1) % 16 == 0:
@@ -131,11 +131,15 @@ def bench_batched(n_inst, steps, cfl, edge_variant, log):
     scr = [torch.empty(2 * s.nv_total, 4, dtype=torch.float64, device="cuda") for s in solvers]
     b.set_states(ws, scr)
     best, tune_ms = autotune_batch(b, cfl, use_cache=False)
+    b.set_schedule(*best)
     log(f"batch autotune: best {best}; " + ", ".join(f"{k}: {v:.2f} ms" for k, v in tune_ms.items()))
     side = torch.cuda.Stream()
     res = {}
-    for label, cand in [("per_instance", (2, 4, 8, 16)), ("per_phase", (1, best[1], best[2], best[3]) if best[0] == 0 else (1, 4, 8, 16)),
-                        ("persistent", best if best[0] == 0 else (0, 4, 8, 16))]:
+    def best_of(sched):
+        c = {k: v for k, v in tune_ms.items() if k[0] == sched}
+        return min(c, key=c.get)
+
+    for label, cand in [("per_instance", best_of(2)), ("per_phase", best_of(1)), ("persistent", best_of(0))]:
         b.set_schedule(*cand)
         for w, w0 in zip(ws, w0s):
             w.copy_(w0)
@@ -337,7 +341,7 @@ def main():
                      "vertex_ms": [round(t, 5) for t in tune["vertex_ms"]]},
     }
     if not args.no_batch:
-        out["batched"] = bench_batched(args.batch_instances, args.batch_steps, 0.5, tune["edge"], log)
+        out["batched"] = bench_batched(args.batch_instances, args.batch_steps, 0.2, tune["edge"], tune["vertex"], log)
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(args.adjoint_N, 20, 5, log)
     if not args.no_cpu_baseline:

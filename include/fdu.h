@@ -243,9 +243,12 @@ fdu_status fdu_kernel_times(fdu_solver* s, void* w, void* scratch, int reps, dou
  * fdu_batch_set_schedule: 0 = one persistent launch per stage for all
  *   instances (tiles in ticket order, per-instance completion counters,
  *   bounded dependency waits); 1 = one launch per phase (ghost, edge, vertex)
- *   for all instances; 2 = every instance's own stage kernels in turn.  Tile
- *   shape: edges_per_thread (edge tile = 256 x that), vertex_passes and
- *   lanes_per_vertex (8 or 16; vertex tile = passes x 256 / lanes).
+ *   for all instances, each phase its own kernel; 2 = every instance's own
+ *   stage kernels in turn.  Tile shape: edges_per_thread (edge tile = 256 x
+ *   that), vertex_passes and vertex_mode (0: strided loops, 16 lanes per
+ *   vertex; 1: strided loops, 8 lanes; 2: pipelined loads, 8 lanes; vertex
+ *   tile = passes x 256 / lanes).  Results equal the plain path's with
+ *   vertex variant 0, 4 and 3 respectively, bit for bit.
  * fdu_batch_step: one SSP-RK3 step of every instance with its own dt =
  *   cfl * min hmin/(|u|+c) (computed on the device), asynchronous on stream.
  * fdu_batch_capture: records nsteps steps on stream (not the default stream)
@@ -259,13 +262,13 @@ fdu_status fdu_batch_create(fdu_batch** out, fdu_solver* const* inst, int n);
 void fdu_batch_destroy(fdu_batch* b);
 fdu_status fdu_batch_set_states(fdu_batch* b, void* const* w, void* const* scratch);
 fdu_status fdu_batch_set_schedule(fdu_batch* b, int schedule, int edges_per_thread, int vertex_passes,
-                                  int lanes_per_vertex);
+                                  int vertex_mode);
 fdu_status fdu_batch_step(fdu_batch* b, double cfl, void* stream);
 fdu_status fdu_batch_capture(fdu_batch* b, double cfl, int nsteps, void* stream);
 fdu_status fdu_batch_launch(fdu_batch* b, void* stream);
 fdu_status fdu_batch_status(fdu_batch* b, int* wait_timeouts, double* dt_host);
 fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, int* grid, int* edges_per_thread,
-                          int* vertex_passes, int* lanes_per_vertex);
+                          int* vertex_passes, int* vertex_mode);
 
 /* Kernel variants and autotuning.  Every variant computes the same residual
  * (the parity tests run each one); they differ in schedule and register use:

@@ -74,13 +74,23 @@ struct BatchTiling {
 
 __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// phase < 0: fused schedule with dynamic tickets and dependency waits;
-// phase 0/1/2: only that phase's tiles, one per block (no waits).
-template <int EV, int LPV>
+// Vertex-tile modes: 0 = strided loops, 16 lanes per vertex; 1 = strided
+// loops, 8 lanes; 2 = pipelined loads, 8 lanes (few registers live across
+// the gathers, for the fused kernel, whose register budget the edge code sets).
+template <int VM>
+struct VertexMode {
+  static constexpr int lpv = VM == 0 ? 16 : 8;
+};
+
+// PH < 0: fused schedule with dynamic tickets and dependency waits; PH 0/1/2:
+// a kernel holding only that phase's code, one tile per block (no waits).
+template <int EV, int VM, int PH>
 __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict__ inst, int n,
                                                      const int* __restrict__ tb, int total, unsigned* ctr, Scheme S,
                                                      int k, double a, double b, const double* __restrict__ dt,
-                                                     int* err, BatchTiling tl, int phase) {
+                                                     int* err, BatchTiling tl) {
+  constexpr int LPV = VertexMode<VM>::lpv;
+  constexpr int phase = PH;
   __shared__ int sh;
   for (int iter = 0;; ++iter) {
     int t;
@@ -100,7 +110,7 @@ __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict
     const BatchInst& I = inst[i];
     double* wprev = k == 0 ? I.w : (k == 1 ? I.w1 : I.w2);
     double* wout = k == 0 ? I.w1 : (k == 1 ? I.w2 : I.w);
-    if (p == 0) {
+    if (PH <= 0 && p == 0) {
       const int g = local * 256 + threadIdx.x;
       if (g < I.ng) {
         double q[4];
@@ -111,7 +121,7 @@ __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict
         store4(wprev, I.nv_real + g, q);
       }
       if (phase < 0) signal_count(&ctr[1 + i]);
-    } else if (p == 1) {
+    } else if ((PH < 0 || PH == 1) && p == 1) {
       if (phase < 0 && I.ng > 0) wait_count(&ctr[1 + i], (unsigned)ceil_div(I.ng, 256), err);
       for (int q = 0; q < tl.ept; ++q) {
         const int e = (local * tl.ept + q) * 256 + threadIdx.x;
@@ -123,14 +133,19 @@ __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict
         }
       }
       if (phase < 0) signal_count(&ctr[1 + n + i]);
-    } else {
+    } else if ((PH < 0 || PH == 2) && p == 2) {
       if (phase < 0) wait_count(&ctr[1 + n + i], (unsigned)ceil_div(I.ne, 256 * tl.ept), err);
       for (int q = 0; q < tl.vp; ++q) {
         const int tt = (local * tl.vp + q) * 256 + threadIdx.x;
         const int v = tt / LPV;
-        vertex_item<double, double, LPV, false>(wprev, I.vptr, I.vcol, I.wfg, I.eptr, I.ecol, I.we, I.cO, I.flux,
-                                                I.nv_real, S.gm1, 1, nullptr, I.w, wout, a, b, dt + i, v,
-                                                tt % LPV);
+        if (VM == 2)
+          vertex_pipe_item<double, double, 8, 3, 6>(wprev, I.vptr, I.vcol, I.wfg, I.eptr, I.ecol, I.we, I.cO, I.flux,
+                                                    I.nv_real, S.gm1, 1, nullptr, I.w, wout, a, b, dt + i, v,
+                                                    tt % LPV);
+        else
+          vertex_item<double, double, LPV, false>(wprev, I.vptr, I.vcol, I.wfg, I.eptr, I.ecol, I.we, I.cO, I.flux,
+                                                  I.nv_real, S.gm1, 1, nullptr, I.w, wout, a, b, dt + i, v,
+                                                  tt % LPV);
       }
     }
   }

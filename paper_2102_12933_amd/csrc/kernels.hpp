@@ -610,15 +610,14 @@ __global__ void __launch_bounds__(256) k_edge_flux_lean(const T* __restrict__ w,
 // of up to MV vertex entries and ME edge entries, then issues all their gathers,
 // then accumulates; entries beyond MV*LPV / ME*LPV go through a tail loop.
 template <class T, class TW, int LPV, int MV, int ME>
-__global__ void __launch_bounds__(256) k_vertex_pipe(const T* __restrict__ w, const int* __restrict__ vptr,
-                                                     const int* __restrict__ vcol, const TW* __restrict__ wfg,
-                                                     const int* __restrict__ eptr, const int* __restrict__ ecol,
-                                                     const TW* __restrict__ we, const double* __restrict__ cO,
-                                                     const double* __restrict__ r, int nreal, double gm1, int mode,
-                                                     T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
-                                                     double a, double b, const double* __restrict__ dt_dev) {
-  const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const int v = t / LPV, lane = t % LPV;
+__device__ __forceinline__ void vertex_pipe_item(const T* __restrict__ w, const int* __restrict__ vptr,
+                                                 const int* __restrict__ vcol, const TW* __restrict__ wfg,
+                                                 const int* __restrict__ eptr, const int* __restrict__ ecol,
+                                                 const TW* __restrict__ we, const double* __restrict__ cO,
+                                                 const double* __restrict__ r, int nreal, double gm1, int mode,
+                                                 T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
+                                                 double a, double b, const double* __restrict__ dt_dev, int v,
+                                                 int lane) {
   const bool active = v < nreal;
   const int vv = active ? v : 0;
   int vb = 0, ve = 0, eb = 0, ee = 0;
@@ -705,6 +704,19 @@ __global__ void __launch_bounds__(256) k_vertex_pipe(const T* __restrict__ w, co
     for (int k = 0; k < 4; ++k) o[k] = a * n[k] + b * (q0[k] + dt * res[k]);
     store4(out, v, o);
   }
+}
+
+template <class T, class TW, int LPV, int MV, int ME>
+__global__ void __launch_bounds__(256) k_vertex_pipe(const T* __restrict__ w, const int* __restrict__ vptr,
+                                                     const int* __restrict__ vcol, const TW* __restrict__ wfg,
+                                                     const int* __restrict__ eptr, const int* __restrict__ ecol,
+                                                     const TW* __restrict__ we, const double* __restrict__ cO,
+                                                     const double* __restrict__ r, int nreal, double gm1, int mode,
+                                                     T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
+                                                     double a, double b, const double* __restrict__ dt_dev) {
+  const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  vertex_pipe_item<T, TW, LPV, MV, ME>(w, vptr, vcol, wfg, eptr, ecol, we, cO, r, nreal, gm1, mode, R, wn, out, a, b,
+                                       dt_dev, t / LPV, t % LPV);
 }
 
 // CFL time step: per-block minima of hmin_v / (|u_v| + c_v), then one block

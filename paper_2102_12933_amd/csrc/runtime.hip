@@ -398,7 +398,7 @@ struct fdu_batch {
   Scheme S{};
   int schedule = 0;     // 0 fused persistent, 1 one launch per phase, 2 per-instance kernels
   BatchTiling tl{4, 8};
-  int lpv = 16;         // lanes per vertex in vertex tiles (16 or 8)
+  int vmode = 0;        // vertex tiles: 0 loop/16 lanes, 1 loop/8 lanes, 2 pipelined/8 lanes
   int grid = 0;         // blocks of the fused launch
   int total = 0, ctiles = 0;
   std::vector<int32_t> h_tb;
@@ -421,7 +421,7 @@ namespace {
 
 void batch_tiles(fdu_batch* b) {
   const int n = b->n;
-  const int per_v = b->tl.vp * (256 / b->lpv);
+  const int per_v = b->tl.vp * (256 / (b->vmode == 0 ? 16 : 8));
   b->h_tb.assign(3 * n + 1, 0);
   int acc = 0;
   for (int p = 0; p < 3; ++p)
@@ -442,36 +442,41 @@ void batch_tiles(fdu_batch* b) {
   b->tbc.upload(tbc.data(), tbc.size());
   int cus = 0, per_cu = 0;
   FDU_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
-  if (b->lpv == 8)
-    FDU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_stage<1, 8>, 256, 0));
-  else
-    FDU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_stage<1, 16>, 256, 0));
+  FDU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_stage<1, 2, -1>, 256, 0));
   b->grid = std::max(1, std::min(b->total, cus * std::max(1, per_cu)));
 }
 
-template <int EV, int LPV>
-void batch_stage_launch(fdu_batch* b, int k, hipStream_t st, int phase, unsigned grid) {
-  hipLaunchKernelGGL((k_batch_stage<EV, LPV>), dim3(grid), dim3(256), 0, st, b->dinst.p, b->n, b->tb.p, b->total,
-                     b->ctr.p, b->S, k, kRK[k][0], kRK[k][1], b->dt.p, b->err.p, b->tl, phase);
+template <int EV, int VM, int PH>
+void batch_stage_launch(fdu_batch* b, int k, hipStream_t st, unsigned grid) {
+  hipLaunchKernelGGL((k_batch_stage<EV, VM, PH>), dim3(grid), dim3(256), 0, st, b->dinst.p, b->n, b->tb.p, b->total,
+                     b->ctr.p, b->S, k, kRK[k][0], kRK[k][1], b->dt.p, b->err.p, b->tl);
+}
+
+template <int EV, int VM>
+void batch_stage_vm(fdu_batch* b, int k, hipStream_t st) {
+  if (b->schedule == 0) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(nblocks(1 + 2 * b->n)), dim3(256), 0, st, b->ctr.p, 1 + 2 * b->n,
+                       (unsigned long long*)nullptr, 0);
+    batch_stage_launch<EV, VM, -1>(b, k, st, (unsigned)b->grid);
+    return;
+  }
+  const int n = b->n;
+  const int t0 = b->h_tb[n] - b->h_tb[0], t1 = b->h_tb[2 * n] - b->h_tb[n], t2 = b->h_tb[3 * n] - b->h_tb[2 * n];
+  if (t0 > 0) batch_stage_launch<EV, VM, 0>(b, k, st, (unsigned)t0);
+  if (t1 > 0) batch_stage_launch<EV, VM, 1>(b, k, st, (unsigned)t1);
+  if (t2 > 0) batch_stage_launch<EV, VM, 2>(b, k, st, (unsigned)t2);
 }
 
 void batch_stage(fdu_batch* b, int k, hipStream_t st) {
   const int ev = b->inst[0]->edge_variant == 1 ? 1 : 0;
-  auto launch = [&](int phase, unsigned grid) {
-    if (ev == 1 && b->lpv == 8) batch_stage_launch<1, 8>(b, k, st, phase, grid);
-    else if (ev == 1) batch_stage_launch<1, 16>(b, k, st, phase, grid);
-    else if (b->lpv == 8) batch_stage_launch<0, 8>(b, k, st, phase, grid);
-    else batch_stage_launch<0, 16>(b, k, st, phase, grid);
-  };
-  if (b->schedule == 0) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(nblocks(1 + 2 * b->n)), dim3(256), 0, st, b->ctr.p, 1 + 2 * b->n,
-                       (unsigned long long*)nullptr, 0);
-    launch(-1, (unsigned)b->grid);
+  if (ev == 1) {
+    if (b->vmode == 2) batch_stage_vm<1, 2>(b, k, st);
+    else if (b->vmode == 1) batch_stage_vm<1, 1>(b, k, st);
+    else batch_stage_vm<1, 0>(b, k, st);
   } else {
-    for (int p = 0; p < 3; ++p) {
-      const int ntiles = b->h_tb[(p + 1) * b->n] - b->h_tb[p * b->n];
-      if (ntiles > 0) launch(p, (unsigned)ntiles);
-    }
+    if (b->vmode == 2) batch_stage_vm<0, 2>(b, k, st);
+    else if (b->vmode == 1) batch_stage_vm<0, 1>(b, k, st);
+    else batch_stage_vm<0, 0>(b, k, st);
   }
   launch_check();
 }
@@ -913,18 +918,18 @@ fdu_status fdu_batch_set_states(fdu_batch* b, void* const* w, void* const* scrat
 }
 
 fdu_status fdu_batch_set_schedule(fdu_batch* b, int schedule, int edges_per_thread, int vertex_passes,
-                                  int lanes_per_vertex) {
+                                  int vertex_mode) {
   return guard([&] {
     need(b != nullptr, "NULL batch");
     need(schedule >= 0 && schedule <= 2, "schedule must be 0, 1 or 2");
     need(edges_per_thread >= 1 && edges_per_thread <= 64, "edges_per_thread out of range");
     need(vertex_passes >= 1 && vertex_passes <= 64, "vertex_passes out of range");
-    need(lanes_per_vertex == 8 || lanes_per_vertex == 16, "lanes_per_vertex must be 8 or 16");
+    need(vertex_mode >= 0 && vertex_mode <= 2, "vertex_mode must be 0, 1 or 2");
     DeviceGuard dg(b->device);
     b->schedule = schedule;
     b->tl.ept = edges_per_thread;
     b->tl.vp = vertex_passes;
-    b->lpv = lanes_per_vertex;
+    b->vmode = vertex_mode;
     batch_tiles(b);
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
@@ -983,7 +988,7 @@ fdu_status fdu_batch_status(fdu_batch* b, int* wait_timeouts, double* dt_host) {
 }
 
 fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, int* grid, int* edges_per_thread,
-                          int* vertex_passes, int* lanes_per_vertex) {
+                          int* vertex_passes, int* vertex_mode) {
   return guard([&] {
     need(b != nullptr, "NULL batch");
     if (schedule) *schedule = b->schedule;
@@ -991,7 +996,7 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
     if (grid) *grid = b->grid;
     if (edges_per_thread) *edges_per_thread = b->tl.ept;
     if (vertex_passes) *vertex_passes = b->tl.vp;
-    if (lanes_per_vertex) *lanes_per_vertex = b->lpv;
+    if (vertex_mode) *vertex_mode = b->vmode;
   });
 }
 

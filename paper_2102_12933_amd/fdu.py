@@ -343,10 +343,9 @@ class Batch:
         _call("fdu_batch_set_states", self.handle, ws, ss)
         self._keep = (list(states), list(scratches))
 
-    def set_schedule(self, schedule: int, edges_per_thread: int = 4, vertex_passes: int = 8,
-                     lanes_per_vertex: int = 16):
+    def set_schedule(self, schedule: int, edges_per_thread: int = 4, vertex_passes: int = 8, vertex_mode: int = 0):
         _call("fdu_batch_set_schedule", self.handle, int(schedule), int(edges_per_thread), int(vertex_passes),
-              int(lanes_per_vertex))
+              int(vertex_mode))
 
     def step(self, cfl: float):
         _call("fdu_batch_step", self.handle, float(cfl), _stream())
@@ -369,7 +368,7 @@ class Batch:
     def info(self):
         vals = [C.c_int() for _ in range(6)]
         _call("fdu_batch_info", self.handle, *[C.byref(v) for v in vals])
-        keys = ["schedule", "total_tiles", "grid", "edges_per_thread", "vertex_passes", "lanes_per_vertex"]
+        keys = ["schedule", "total_tiles", "grid", "edges_per_thread", "vertex_passes", "vertex_mode"]
         return {k: v.value for k, v in zip(keys, vals)}
 
     def __del__(self):

@@ -2,7 +2,7 @@
 
 The kernel variants of a single solver are tuned inside the library
 (fdu_autotune).  For a batch, this module times candidate (schedule, edges per
-thread, vertex passes, lanes per vertex) settings with HIP events on the
+thread, vertex passes, vertex mode) settings with HIP events on the
 instances' real data and keeps the fastest; results are cached in a JSON file
 keyed by the device name and the batch's size class, so a later run with the
 same shape reuses the choice without timing.
@@ -14,7 +14,9 @@ import os
 
 import torch
 
-CANDIDATES = [(0, 4, 8, 16), (0, 1, 4, 16), (0, 16, 32, 16), (0, 4, 8, 8), (1, 4, 8, 16), (2, 4, 8, 16)]
+# (schedule, edges per thread, vertex passes, vertex mode)
+CANDIDATES = [(0, 4, 8, 2), (0, 16, 16, 2), (0, 4, 8, 0), (0, 16, 32, 1), (1, 4, 8, 0), (1, 4, 8, 2), (1, 16, 16, 1),
+              (2, 4, 8, 0)]
 CACHE = os.environ.get("FDU_TUNING_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "fdu_tuning.json"))
 
 

@@ -48,15 +48,15 @@ def plain_steps(inst, nsteps, cfl):
 
 
 @pytest.mark.parametrize("edge_variant", [0, 1])
-@pytest.mark.parametrize("schedule,ept,vp,lpv", [(0, 4, 8, 16), (0, 1, 1, 8), (1, 4, 8, 16), (2, 4, 8, 16),
-                                                 (0, 16, 32, 16)])
-def test_batch_equals_plain(edge_variant, schedule, ept, vp, lpv):
+@pytest.mark.parametrize("schedule,ept,vp,vmode", [(0, 4, 8, 0), (0, 1, 1, 1), (0, 4, 8, 2), (1, 4, 8, 0),
+                                                   (1, 16, 16, 2), (2, 4, 8, 0), (0, 16, 32, 0)])
+def test_batch_equals_plain(edge_variant, schedule, ept, vp, vmode):
     fdu = _fdu()
-    # the plain path's vertex kernel with the same lanes per vertex sums in the same order
-    inst = build_instances(SPECS, edge_variant, vertex_variant=0 if lpv == 16 else 4)
+    # the plain path's vertex kernel with the same lanes and load order sums in the same order
+    inst = build_instances(SPECS, edge_variant, vertex_variant={0: 0, 1: 4, 2: 3}[vmode])
     ref = plain_steps(inst, 3, 0.5)
     b = fdu.Batch([s for s, _ in inst])
-    b.set_schedule(schedule, ept, vp, lpv)
+    b.set_schedule(schedule, ept, vp, vmode)
     ws = [w0.clone() for _, w0 in inst]
     scr = [torch.empty(2 * s.nv_total, 4, dtype=torch.float64, device="cuda") for s, _ in inst]
     b.set_states(ws, scr)
@@ -72,7 +72,7 @@ def test_batch_graph_replays_match_eager():
     fdu = _fdu()
     inst = build_instances(SPECS[:3])
     b = fdu.Batch([s for s, _ in inst])
-    b.set_schedule(0, 4, 8, 16)
+    b.set_schedule(0, 4, 8, 0)
     ws = [w0.clone() for _, w0 in inst]
     scr = [torch.empty(2 * s.nv_total, 4, dtype=torch.float64, device="cuda") for s, _ in inst]
     b.set_states(ws, scr)

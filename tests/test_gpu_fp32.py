@@ -1,0 +1,55 @@
+"""FP32-storage path (state, geometry, weights and residual stored in FP32;
+arithmetic and edge fluxes in FP64) against the FP64 oracle fed the same
+FP32-representable state: 1e-5 relative per component.  The bound comes from
+rounding the least-squares weights and geometry to FP32 (relative 6e-8, times
+the weights' cancellation factor sum|w|h/|div h| of order 10-100)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.solver import Oracle
+from paper_2102_12933_amd.inputs import make_mesh, sod_state, vortex_state
+from tests._helpers import rel_err_per_component
+from tests.test_gpu_parity import perturbed_sod
+
+pytestmark = pytest.mark.gpu
+TOL32 = 1e-5
+
+
+def _case(N, periodic, ghosts, deg, state, seed=0):
+    from paper_2102_12933_amd import fdu
+    m = make_mesh(N, L=10.0 if periodic else 1.0, periodic=periodic, seed=seed, ghost_layers=ghosts)
+    prep = fdu.Prep(m, deg=deg, reorder=1)
+    perm = prep.arrays()["perm"]
+    s = fdu.Solver(prep, device=0, precision="f32")
+    w0 = vortex_state(m, beta=5.0, mach=0.5) if state == "vortex" else perturbed_sod(m)
+    w32 = w0.astype(np.float32).astype(np.float64)
+    return m, perm, s, w32
+
+
+@pytest.mark.parametrize("N,per,G,deg,state", [(33, True, 0, 3, "vortex"), (33, True, 0, 5, "vortex"),
+                                               (129, True, 0, 5, "vortex"), (24, False, 4, 5, "sod")])
+def test_fp32_residual(N, per, G, deg, state):
+    m, perm, s, w32 = _case(N, per, G, deg, state)
+    for ev in range(2):
+        s.set_variants(ev, 0)
+        R = s.residual(torch.from_numpy(w32[perm].astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
+        Ro = Oracle(m, deg=deg).residual(torch.from_numpy(w32)).numpy()[perm[:m.nv_real]]
+        err = rel_err_per_component(R, Ro)
+        print(N, deg, state, "edge variant", ev, "fp32 storage rel err", err)
+        assert err.max() <= TOL32
+
+
+def test_fp32_rk_steps():
+    m, perm, s, w32 = _case(33, True, 0, 3, "vortex")
+    o = Oracle(m, deg=3)
+    w = torch.from_numpy(w32[perm].astype(np.float32)).cuda()
+    scratch = torch.empty(2 * m.nv, 4, dtype=torch.float32, device="cuda")
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    wo = torch.from_numpy(w32.copy())
+    for _ in range(5):
+        s.rk_step(w, scratch, dt, cfl=0.5)
+        wo = o.rk3_step(wo, o.cfl_dt(wo, 0.5))
+    err = rel_err_per_component(w.cpu().numpy().astype(np.float64), wo.numpy()[perm])
+    print("5 steps fp32 storage rel err", err)
+    assert err.max() <= TOL32
