@@ -102,7 +102,7 @@ void fdu_default_params(fdu_params* out);
  *   nv_total - nv_real; periodic != 0 wraps displacements to the nearest image
  *   in the box Lx x Ly.  deg = polynomial degree (3..6), level = 0 (automatic:
  *   one-level for deg <= 3, two-level otherwise), 1 or 2; reorder = 0 natural,
- *   1 reverse Cuthill-McKee.  nthreads <= 0 uses all host cores.
+ *   1 reverse Cuthill-McKee, 2 Hilbert curve through the vertex coordinates.  nthreads <= 0 uses all host cores.
  * Errors: FDU_ERR_INVALID_ARG for inconsistent sizes or ids, FDU_ERR_NUMERIC
  * when an edge has no admissible stencil continuation or a least-squares
  * matrix is rank deficient.
@@ -233,6 +233,23 @@ fdu_status fdu_rk_step_vjp(fdu_solver* s, void* w_n, const void* wbar_np1, void*
  * The timed work equals the work of the corresponding compute calls. */
 fdu_status fdu_kernel_times(fdu_solver* s, void* w, void* scratch, int reps, double* avg_ms, void* stream);
 
+/* Live kernel timer: measurement aid for the ordinary compute calls.
+ * fdu_kernel_timer_start: from now on every launch of the ghost-fill, edge-flux,
+ * vertex and CFL kernels by this solver (fdu_fill_ghosts, fdu_edge_fluxes,
+ * fdu_residual, fdu_cfl_dt, fdu_rk_stage, fdu_rk_step) is bracketed by a pair
+ * of HIP events recorded on the stream of that call, for the first `capacity`
+ * (1 .. 2^20) launches of each kind; nothing is recorded while the stream is
+ * being captured into a graph.  Creates the events on first use (set-up,
+ * synchronous); the solver owns them until fdu_destroy.
+ * fdu_kernel_timer_stop: stops recording, waits for the last recorded event and
+ * writes, for ghost fill, edge flux, vertex step and CFL reduction in that
+ * order, the mean bracketed duration in milliseconds to avg_ms[0..3] and the
+ * number of launches timed to counts[0..3] (0 and 0.0 when none).  Returns
+ * FDU_ERR_INVALID_ARG when the timer is not running or a pointer is NULL.
+ * The event records add a few microseconds per launch to the stream. */
+fdu_status fdu_kernel_timer_start(fdu_solver* s, int capacity);
+fdu_status fdu_kernel_timer_stop(fdu_solver* s, double* avg_ms, int* counts);
+
 /* ------------------------------------------------------------------------
  * Batches: many FP64 instances (finalized solvers on one device with equal
  * scheme parameters and edge variant) advanced together.
@@ -277,7 +294,10 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
  *   vertex: 0 = 16 lanes per vertex, strided loops; 1, 2, 3 = 16, 32, 8 lanes
  *           per vertex, all index/weight loads issued before all gathers;
  *           4, 5 = strided loops with 8 and 4 lanes per vertex; 6, 7 = strided
- *           loops with 16 and 8 lanes and non-temporal stencil-array loads.
+ *           loops with 16 and 8 lanes and non-temporal stencil-array loads;
+ *           8, 9 = 16 and 8 lanes per vertex in pairs, each lane of a pair
+ *           gathering one 16-byte half of a stencil row (half the gather
+ *           instructions), all loads issued before the arithmetic.
  * fdu_set_variants / fdu_get_variants select and report them (n_edge, n_vertex:
  * how many exist).  fdu_autotune times every edge variant and then every vertex
  * variant on the given state with fdu_kernel_times (reps launches each),

@@ -13,10 +13,9 @@
 //   wbar_v  = (df/dw)^T fbar_v + (dg/dw)^T gbar_v + sum of v's slots  (k_vertex_vjp)
 //   ghosts  copy their mirror source: a ghost's cotangent goes to its source
 //           with the same momentum signs; ghost rows end at zero  (k_ghost_vjp)
-// The edge-flux reverse sweep is written by hand for the NU-WENO5 nonlinear
-// weights and the characteristic projections; the Roe-averaged frame and the
-// Riemann flux (functions of 8 inputs) are differentiated with forward-mode
-// dual numbers.
+// The edge-flux reverse sweep is written out by hand: Riemann flux (Roe with
+// Harten's fix, or Rusanov), back-projection, NU-WENO5 nonlinear weights,
+// characteristic projection and the Roe-averaged frame they all depend on.
 #pragma once
 
 #include "kernels.hpp"
@@ -76,7 +75,193 @@ FDU_HD void weno_eval_T(const WenoGeom& G, const double u[5], double eps, int po
   }
 }
 
-using D8 = Dual<8>;
+// ---------------------------------------------------------------------------
+// Reverse mode, written out by hand: every *_T function below takes the
+// cotangent of a forward function's output and accumulates the cotangents of
+// its inputs (the forward values are recomputed, nothing is stored).
+
+// Cotangents of the characteristic frame's fields.
+struct FrameBar {
+  double u = 0.0, v = 0.0, H = 0.0, c = 0.0, un = 0.0, ut = 0.0, q2 = 0.0;
+};
+
+// Frame cotangents of o = to_char(F, q) for fixed q.
+FDU_HD void to_char_frame_T(const Frame& F, double gm1, const double q[4], const double ob[4], FrameBar& Fb) {
+  const double ic = 1.0 / F.c;
+  const double b1 = gm1 * ic * ic;
+  const double mv = F.u * q[1] + F.v * q[2];
+  const double nm = F.nx * q[1] + F.ny * q[2];
+  const double coreb = 0.5 * ob[0] - ob[1] + 0.5 * ob[3];   // core = b1 (q2 rho - u.m + rhoE)
+  const double xb = 0.5 * (ob[0] - ob[3]);                  // x = (u_n rho - n.m) / c
+  Fb.ut -= ob[2] * q[0];
+  Fb.un += xb * ic * q[0];
+  const double b1b = coreb * (F.q2 * q[0] - mv + q[3]);
+  Fb.q2 += coreb * b1 * q[0];
+  const double mvb = -coreb * b1;
+  Fb.u += mvb * q[1];
+  Fb.v += mvb * q[2];
+  const double icb = xb * (F.un * q[0] - nm) + b1b * 2.0 * gm1 * ic;
+  Fb.c -= icb * ic * ic;
+}
+
+// Frame cotangents of q = from_char(F, a) for fixed a.
+FDU_HD void from_char_frame_T(const Frame& F, const double a[4], const double qb[4], FrameBar& Fb) {
+  const double s = a[0] + a[3], d = a[3] - a[0];
+  Fb.u += qb[1] * (s + a[1]);
+  Fb.v += qb[2] * (s + a[1]);
+  Fb.c += (qb[1] * F.nx + qb[2] * F.ny + qb[3] * F.un) * d;
+  Fb.H += qb[3] * s;
+  Fb.un += qb[3] * F.c * d;
+  Fb.q2 += qb[3] * a[1];
+  Fb.ut += qb[3] * a[2];
+}
+
+// One side of the Roe average: cotangents of its velocity (usb, vsb),
+// enthalpy (Hsb) and sqrt(rho) (rsb) to the conservative state q.
+// H_s = gamma E / rho - (gamma - 1) (u^2 + v^2) / 2.
+FDU_HD void roe_side_T(const double q[4], double gm1, double usb, double vsb, double Hsb, double rsb, double qb[4]) {
+  const double iq = 1.0 / q[0];
+  const double us = q[1] * iq, vs = q[2] * iq;
+  const double gam = gm1 + 1.0;
+  usb -= Hsb * gm1 * us;
+  vsb -= Hsb * gm1 * vs;
+  qb[0] += -Hsb * gam * q[3] * iq * iq - (usb * us + vsb * vs) * iq + rsb * 0.5 / ::sqrt(q[0]);
+  qb[1] += usb * iq;
+  qb[2] += vsb * iq;
+  qb[3] += Hsb * gam * iq;
+}
+
+// Frame cotangents back to the two states the frame was averaged from.
+FDU_HD void roe_frame_T(const Frame& F, const double a[4], const double b[4], double gm1, const FrameBar& Fb,
+                        double ab[4], double bb[4]) {
+  // derived fields: u_n, u_t, c, q2 -> (u, v, H)
+  double Ub = Fb.u + Fb.un * F.nx - Fb.ut * F.ny;
+  double Vb = Fb.v + Fb.un * F.ny + Fb.ut * F.nx;
+  const double t = Fb.c * 0.5 * gm1 / F.c;       // c = sqrt(gm1 (H - q2))
+  const double Hb = Fb.H + t;
+  const double q2b = Fb.q2 - t;
+  Ub += q2b * F.u;
+  Vb += q2b * F.v;
+  // (u, v, H) = (ra x_a + rb x_b) / (ra + rb)
+  const double ra = ::sqrt(a[0]), rb = ::sqrt(b[0]), is = 1.0 / (ra + rb);
+  const double ia = 1.0 / a[0], ib = 1.0 / b[0];
+  const double ua = a[1] * ia, va = a[2] * ia, ubs = b[1] * ib, vbs = b[2] * ib;
+  const double Ha = (gm1 + 1.0) * a[3] * ia - 0.5 * gm1 * (ua * ua + va * va);
+  const double Hbs = (gm1 + 1.0) * b[3] * ib - 0.5 * gm1 * (ubs * ubs + vbs * vbs);
+  const double wa = ra * is, wb = rb * is;
+  const double rab = (Ub * (ua - F.u) + Vb * (va - F.v) + Hb * (Ha - F.H)) * is;
+  const double rbb = (Ub * (ubs - F.u) + Vb * (vbs - F.v) + Hb * (Hbs - F.H)) * is;
+  roe_side_T(a, gm1, Ub * wa, Vb * wa, Hb * wa, rab, ab);
+  roe_side_T(b, gm1, Ub * wb, Vb * wb, Hb * wb, rbb, bb);
+}
+
+// q cotangent of normal_flux(q): Fb on the flux, plus direct cotangents unb on
+// u_n and pb on the pressure.
+FDU_HD void normal_flux_T(const double q[4], double nx, double ny, double gm1, const double Fb[4], double unb,
+                          double pb, double qb[4]) {
+  const double ir = 1.0 / q[0];
+  const double u = q[1] * ir, v = q[2] * ir;
+  const double p = gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * v));
+  const double un = u * nx + v * ny;
+  unb += Fb[0] * q[0] + Fb[1] * q[1] + Fb[2] * q[2] + Fb[3] * (q[3] + p);
+  pb += Fb[1] * nx + Fb[2] * ny + Fb[3] * un;
+  qb[0] += Fb[0] * un - unb * un * ir + pb * gm1 * 0.5 * (u * u + v * v);
+  qb[1] += Fb[1] * un + unb * nx * ir - pb * gm1 * u;
+  qb[2] += Fb[2] * un + unb * ny * ir - pb * gm1 * v;
+  qb[3] += Fb[3] * un + pb * gm1;
+}
+
+// Cotangents of the midpoint states (wl, wr) for the flux cotangent ob.
+FDU_HD void riemann_flux_T(const double wl[4], const double wr[4], double nx, double ny, const Scheme& S,
+                           const double ob[4], double wlb[4], double wrb[4]) {
+  double hb[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    hb[k] = 0.5 * ob[k];          // out = (Fl + Fr) / 2 - dissipation / 2
+    wlb[k] = 0.0;
+    wrb[k] = 0.0;
+  }
+  if (S.riemann == 1) {
+    double Fl[4], Fr[4], unl, unr, c2l, c2r;
+    normal_flux<double>(wl, nx, ny, S.gm1, Fl, unl, c2l);
+    normal_flux<double>(wr, nx, ny, S.gm1, Fr, unr, c2r);
+    const double cl = ::sqrt(c2l), cr = ::sqrt(c2r);
+    const double sl = ::fabs(unl) + cl, sr = ::fabs(unr) + cr;
+    const bool left = sl >= sr;
+    const double sm = left ? sl : sr;
+    double smb = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      smb -= 0.5 * ob[k] * (wr[k] - wl[k]);
+      wlb[k] += 0.5 * sm * ob[k];
+      wrb[k] -= 0.5 * sm * ob[k];
+    }
+    // s = |u_n| + sqrt(gamma p / rho) of the side that gave the maximum
+    const double* q = left ? wl : wr;
+    const double un = left ? unl : unr, c = left ? cl : cr, c2 = left ? c2l : c2r;
+    const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+    const double c2b = smb * 0.5 / c;
+    double qb[4] = {-c2b * c2 / q[0], 0.0, 0.0, 0.0};
+    normal_flux_T(q, nx, ny, S.gm1, zero, smb * (un < 0.0 ? -1.0 : 1.0), c2b * (S.gm1 + 1.0) / q[0], qb);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (left) wlb[k] += qb[k]; else wrb[k] += qb[k];
+    }
+    normal_flux_T(wl, nx, ny, S.gm1, hb, 0.0, 0.0, wlb);
+    normal_flux_T(wr, nx, ny, S.gm1, hb, 0.0, 0.0, wrb);
+    return;
+  }
+  // Roe with Harten's fix: dissipation = from_char(F, h * to_char(F, wr - wl))
+  const Frame F = roe_frame<double>(wl, wr, nx, ny, S.gm1);
+  double dq[4], a[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) dq[k] = wr[k] - wl[k];
+  to_char(F, S.gm1, dq, a);
+  const double delta = S.efrac * F.c;
+  const double lam[4] = {F.un - F.c, F.un, F.un, F.un + F.c};
+  double h[4], ap[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    h[k] = harten<double>(lam[k], delta);
+    ap[k] = a[k] * h[k];
+  }
+  double db[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) db[k] = -0.5 * ob[k];
+  FrameBar Fb;
+  double apb[4];
+  from_char_T(F, db, apb);
+  from_char_frame_T(F, ap, db, Fb);
+  double ab[4], deltab = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    ab[k] = apb[k] * h[k];
+    const double hk = apb[k] * a[k];
+    const double l = lam[k];
+    double lb;
+    if (::fabs(l) < delta) {         // h = (l^2 + delta^2) / (2 delta)
+      lb = hk * l / delta;
+      deltab += hk * (delta * delta - l * l) / (2.0 * delta * delta);
+    } else {                         // h = |l|
+      lb = l < 0.0 ? -hk : hk;
+    }
+    Fb.un += lb;
+    if (k == 0) Fb.c -= lb;
+    if (k == 3) Fb.c += lb;
+  }
+  Fb.c += S.efrac * deltab;
+  double dqb[4] = {0.0, 0.0, 0.0, 0.0};
+  to_char_T_acc(F, S.gm1, ab, dqb);
+  to_char_frame_T(F, S.gm1, dq, ab, Fb);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    wrb[k] += dqb[k];
+    wlb[k] -= dqb[k];
+  }
+  roe_frame_T(F, wl, wr, S.gm1, Fb, wlb, wrb);
+  normal_flux_T(wl, nx, ny, S.gm1, hb, 0.0, 0.0, wlb);
+  normal_flux_T(wr, nx, ny, S.gm1, hb, 0.0, 0.0, wrb);
+}
 
 // Cotangents Wb of the six stencil states of one edge for the flux cotangent
 // ob (the reverse of edge_flux_one).
@@ -114,48 +299,31 @@ FDU_HD void edge_vjp_one(const double W[6][4], const double g[6], const double o
       for (int k = 0; k < 4; ++k) wr[k] = W[3][k];
   }
 
+  // ---- Riemann flux
+  double wlb[4], wrb[4];
+  riemann_flux_T(wl, wr, nx, ny, S, ob, wlb, wrb);
 #pragma unroll
   for (int s = 0; s < 6; ++s)
 #pragma unroll
     for (int k = 0; k < 4; ++k) Wb[s][k] = 0.0;
-
-  // ---- Riemann flux: Jacobian by dual numbers over (wl, wr)
-  double wlb[4], wrb[4];
-  {
-    D8 a[4], b[4], o[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      a[k] = D8(wl[k]);
-      a[k].d[k] = 1.0;
-      b[k] = D8(wr[k]);
-      b[k].d[4 + k] = 1.0;
-    }
-    riemann_flux<D8>(a, b, nx, ny, S, o);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      double sl = 0.0, sr = 0.0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        sl += ob[i] * o[i].d[k];
-        sr += ob[i] * o[i].d[4 + k];
-      }
-      wlb[k] = sl;
-      wrb[k] = sr;
-    }
-  }
+  // ---- back-projection (or the fallback's copy of the end state)
+  FrameBar Fb;
+  double clb[4] = {0.0, 0.0, 0.0, 0.0}, crb[4] = {0.0, 0.0, 0.0, 0.0};
   if (fl) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) Wb[2][k] += wlb[k];
+  } else {
+    from_char_T(F, wlb, clb);
+    from_char_frame_T(F, cl, wlb, Fb);
   }
   if (fr) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) Wb[3][k] += wrb[k];
+  } else {
+    from_char_T(F, wrb, crb);
+    from_char_frame_T(F, cr, wrb, Fb);
   }
-
-  // ---- back-projection and WENO, at the fixed frame
-  double clb[4] = {0.0, 0.0, 0.0, 0.0}, crb[4] = {0.0, 0.0, 0.0, 0.0};
-  if (!fl) from_char_T(F, wlb, clb);
-  if (!fr) from_char_T(F, wrb, crb);
+  // ---- NU-WENO5 along the stencil, one characteristic component at a time
   double Cb[6][4];
 #pragma unroll
   for (int s = 0; s < 6; ++s)
@@ -173,62 +341,14 @@ FDU_HD void edge_vjp_one(const double W[6][4], const double g[6], const double o
 #pragma unroll
     for (int m = 0; m < 5; ++m) Cb[5 - m][c] += ubr[m];
   }
-  // characteristic projection at the fixed frame
+  // ---- characteristic projection: states at the fixed frame, then the frame
 #pragma unroll
-  for (int s = 0; s < 6; ++s) to_char_T_acc(F, S.gm1, Cb[s], Wb[s]);
-
-  // ---- frame dependence on the end states (W[2], W[3]) by dual numbers
-  {
-    D8 a[4], b[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      a[k] = D8(W[2][k]);
-      a[k].d[k] = 1.0;
-      b[k] = D8(W[3][k]);
-      b[k].d[4 + k] = 1.0;
-    }
-    const FrameT<D8> Fd = roe_frame<D8>(a, b, nx, ny, S.gm1);
-    double fb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    auto acc = [&](const D8 o[4], const double cot[4]) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        double t = 0.0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) t += cot[i] * o[i].d[j];
-        fb[j] += t;
-      }
-    };
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      D8 q[4], o[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) q[k] = D8(W[s][k]);
-      to_char<D8>(Fd, S.gm1, q, o);
-      acc(o, Cb[s]);
-    }
-    if (!fl) {
-      D8 q[4], o[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) q[k] = D8(cl[k]);
-      from_char<D8>(Fd, q, o);
-      acc(o, wlb);
-    }
-    if (!fr) {
-      D8 q[4], o[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) q[k] = D8(cr[k]);
-      from_char<D8>(Fd, q, o);
-      acc(o, wrb);
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      Wb[2][k] += fb[k];
-      Wb[3][k] += fb[4 + k];
-    }
+  for (int s = 0; s < 6; ++s) {
+    to_char_T_acc(F, S.gm1, Cb[s], Wb[s]);
+    to_char_frame_T(F, S.gm1, W[s], Cb[s], Fb);
   }
+  roe_frame_T(F, W[2], W[3], S.gm1, Fb, Wb[2], Wb[3]);
 }
-
-
 
 // rbar_k = -sum_{O uses k} we_Ok Rbar_O (transposed edge CSR)
 template <class T, class TW>

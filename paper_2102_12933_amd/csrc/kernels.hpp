@@ -719,6 +719,153 @@ __global__ void __launch_bounds__(256) k_vertex_pipe(const T* __restrict__ w, co
                                        dt_dev, t / LPV, t % LPV);
 }
 
+// Vertex step on half rows.  The texture data path returns about one cache
+// line per cycle for a gather, so a wave-wide 16-byte gather whose 64 lanes
+// hit 64 different rows costs ~64 cycles, and a 32-byte row needs two of
+// them.  Here two adjacent lanes share each stencil entry and load one 16-byte
+// half of its row each: one gather instruction covers 32 rows in 32 lines.
+// Lane parity h owns components 2h and 2h+1 of the accumulated divergence;
+// for the vertex terms the two lanes swap halves (a DPP lane permutation, no
+// memory) so that each can evaluate the Euler fluxes of the full state.
+__device__ __forceinline__ double pair_swap(double x) {
+  // quad_perm(1, 0, 3, 2): lane i reads lane i ^ 1
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ void load_half(const double* __restrict__ w, int v, int h, double q[2]) {
+  const double2 a = reinterpret_cast<const double2*>(w + 4 * (size_t)v)[h];
+  q[0] = a.x; q[1] = a.y;
+}
+__device__ __forceinline__ void load_half(const float* __restrict__ w, int v, int h, double q[2]) {
+  const float2 a = reinterpret_cast<const float2*>(w + 4 * (size_t)v)[h];
+  q[0] = a.x; q[1] = a.y;
+}
+__device__ __forceinline__ void store_half(double* __restrict__ w, int v, int h, double a, double b) {
+  reinterpret_cast<double2*>(w + 4 * (size_t)v)[h] = make_double2(a, b);
+}
+__device__ __forceinline__ void store_half(float* __restrict__ w, int v, int h, double a, double b) {
+  reinterpret_cast<float2*>(w + 4 * (size_t)v)[h] = make_float2((float)a, (float)b);
+}
+
+// Accumulates wf (f_j - f_O) + wg (g_j - g_O) for components (2h, 2h+1) from
+// this lane's half row x of w_j (the partner lane holds the other half).
+__device__ __forceinline__ void pair_vertex_term(const double x[2], int h, double gm1, double wf, double wg,
+                                                 const double f0[2], const double g0[2], bool use, double acc[2]) {
+  const double y0 = pair_swap(x[0]), y1 = pair_swap(x[1]);
+  const double q0 = h ? y0 : x[0], q1 = h ? y1 : x[1], q2 = h ? x[0] : y0, q3 = h ? x[1] : y1;
+  const double ir = 1.0 / q0;
+  const double u = q1 * ir, v = q2 * ir;
+  const double p = gm1 * (q3 - 0.5 * (q1 * u + q2 * v));
+  const double ep = q3 + p;
+  // h = 0: f = (m_x, m_x u + p), g = (m_y, m_y u); h = 1: f = (m_x v, (E+p) u), g = (m_y v + p, (E+p) v)
+  const double fa = h ? q1 * v : q1, fb = h ? ep * u : q1 * u + p;
+  const double ga = h ? q2 * v + p : q2, gb = h ? ep * v : q2 * u;
+  if (use) {
+    acc[0] += wf * (fa - f0[0]) + wg * (ga - g0[0]);
+    acc[1] += wf * (fb - f0[1]) + wg * (gb - g0[1]);
+  }
+}
+
+template <class T, class TW, int LPV, int MV, int ME>
+__device__ __forceinline__ void vertex_pair_item(const T* __restrict__ w, const int* __restrict__ vptr,
+                                                 const int* __restrict__ vcol, const TW* __restrict__ wfg,
+                                                 const int* __restrict__ eptr, const int* __restrict__ ecol,
+                                                 const TW* __restrict__ we, const double* __restrict__ cO,
+                                                 const double* __restrict__ r, int nreal, double gm1, int mode,
+                                                 T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
+                                                 double a, double b, const double* __restrict__ dt_dev, int v,
+                                                 int lane) {
+  constexpr int NS = LPV / 2;   // entry slots per pass
+  const int h = lane & 1, slot = lane >> 1;
+  const bool active = v < nreal;
+  const int vv = active ? v : 0;
+  int vb = 0, ve = 0, eb = 0, ee = 0;
+  if (active) {
+    vb = vptr[v]; ve = vptr[v + 1];
+    eb = eptr[v]; ee = eptr[v + 1];
+  }
+  int jv[MV], ke[ME];
+  double wf[MV], wg[MV], cw[ME];
+#pragma unroll
+  for (int s = 0; s < MV; ++s) {
+    const int p = vb + slot + s * NS;
+    jv[s] = p < ve ? vcol[p] : -1;
+    wf[s] = p < ve ? (double)wfg[2 * (size_t)p] : 0.0;
+    wg[s] = p < ve ? (double)wfg[2 * (size_t)p + 1] : 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < ME; ++s) {
+    const int p = eb + slot + s * NS;
+    ke[s] = p < ee ? ecol[p] : -1;
+    cw[s] = p < ee ? (double)we[p] : 0.0;
+  }
+  double hv[MV][2], hr[ME][2];
+#pragma unroll
+  for (int s = 0; s < MV; ++s) load_half(w, jv[s] >= 0 ? jv[s] : vv, h, hv[s]);
+#pragma unroll
+  for (int s = 0; s < ME; ++s) load_half(r, ke[s] >= 0 ? ke[s] : 0, h, hr[s]);
+  double q0[4], f0[4], g0[4];
+  load4(w, vv, q0);
+  euler_fg(q0, gm1, f0, g0);
+  const double f0h[2] = {h ? f0[2] : f0[0], h ? f0[3] : f0[1]};
+  const double g0h[2] = {h ? g0[2] : g0[0], h ? g0[3] : g0[1]};
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < MV; ++s) pair_vertex_term(hv[s], h, gm1, wf[s], wg[s], f0h, g0h, jv[s] >= 0, acc);
+#pragma unroll
+  for (int s = 0; s < ME; ++s) {
+    acc[0] += cw[s] * hr[s][0];
+    acc[1] += cw[s] * hr[s][1];
+  }
+  // tails (rare: stencils larger than the unrolled slots); both lanes of a
+  // pair run the same trip count, so the half swap always finds its partner
+  for (int p = vb + slot + MV * NS; p < ve; p += NS) {
+    double x[2];
+    load_half(w, vcol[p], h, x);
+    pair_vertex_term(x, h, gm1, (double)wfg[2 * (size_t)p], (double)wfg[2 * (size_t)p + 1], f0h, g0h, true, acc);
+  }
+  for (int p = eb + slot + ME * NS; p < ee; p += NS) {
+    double x[2];
+    load_half(r, ecol[p], h, x);
+    const double c = (double)we[p];
+    acc[0] += c * x[0];
+    acc[1] += c * x[1];
+  }
+  // reduce over the lanes of equal parity
+#pragma unroll
+  for (int m = LPV / 2; m >= 2; m >>= 1) {
+    acc[0] += __shfl_xor(acc[0], m, LPV);
+    acc[1] += __shfl_xor(acc[1], m, LPV);
+  }
+  if (!active || slot != 0) return;
+  const double cx = cO[2 * (size_t)v], cy = cO[2 * (size_t)v + 1];
+  const double ra = -(acc[0] - (cx * f0h[0] + cy * g0h[0]));
+  const double rb = -(acc[1] - (cx * f0h[1] + cy * g0h[1]));
+  if (mode == 0) {
+    store_half(R, v, h, ra, rb);
+  } else {
+    const double dt = *dt_dev;
+    double n[2] = {0.0, 0.0};
+    if (a != 0.0) load_half(wn, v, h, n);
+    const double qa = h ? q0[2] : q0[0], qb = h ? q0[3] : q0[1];
+    store_half(out, v, h, a * n[0] + b * (qa + dt * ra), a * n[1] + b * (qb + dt * rb));
+  }
+}
+
+template <class T, class TW, int LPV, int MV, int ME>
+__global__ void __launch_bounds__(256) k_vertex_pair(const T* __restrict__ w, const int* __restrict__ vptr,
+                                                     const int* __restrict__ vcol, const TW* __restrict__ wfg,
+                                                     const int* __restrict__ eptr, const int* __restrict__ ecol,
+                                                     const TW* __restrict__ we, const double* __restrict__ cO,
+                                                     const double* __restrict__ r, int nreal, double gm1, int mode,
+                                                     T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
+                                                     double a, double b, const double* __restrict__ dt_dev) {
+  const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  vertex_pair_item<T, TW, LPV, MV, ME>(w, vptr, vcol, wfg, eptr, ecol, we, cO, r, nreal, gm1, mode, R, wn, out, a, b,
+                                       dt_dev, t / LPV, t % LPV);
+}
+
 // CFL time step: per-block minima of hmin_v / (|u_v| + c_v), then one block
 // reduces them and writes cfl * min.
 template <class T>

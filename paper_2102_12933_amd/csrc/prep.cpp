@@ -492,6 +492,52 @@ std::vector<int32_t> rcm_order(const Mesh& m) {
   return order;
 }
 
+// Position of the cell (x, y) along the Hilbert curve that fills a 2^b x 2^b
+// grid (the usual quadrant recursion: at each scale take the quadrant's rank in
+// the curve's visiting order, then rotate/reflect the coordinates so the
+// sub-square is traversed in the base orientation).
+uint64_t hilbert_index(uint32_t x, uint32_t y, int b) {
+  const uint32_t n = 1u << b;
+  uint64_t d = 0;
+  for (uint32_t s = n >> 1; s > 0; s >>= 1) {
+    const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+    d += (uint64_t)s * s * ((3u * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = n - 1 - x;
+        y = n - 1 - y;
+      }
+      std::swap(x, y);
+    }
+  }
+  return d;
+}
+
+// Real vertices in the order of the Hilbert curve through their coordinates
+// (bounding box of the real vertices, 2^16 cells per side; ties by id): a run
+// of consecutive ids is a compact patch of the mesh.
+std::vector<int32_t> hilbert_order(const Mesh& m, const double* xy) {
+  const int64_t n = m.nreal;
+  double x0 = xy[0], x1 = xy[0], y0 = xy[1], y1 = xy[1];
+  for (int64_t v = 0; v < n; ++v) {
+    x0 = std::min(x0, xy[2 * v]); x1 = std::max(x1, xy[2 * v]);
+    y0 = std::min(y0, xy[2 * v + 1]); y1 = std::max(y1, xy[2 * v + 1]);
+  }
+  const int b = 16;
+  const double span = std::max(x1 - x0, y1 - y0);
+  const double sc = span > 0 ? (double)((1u << b) - 1) / span : 0.0;
+  std::vector<std::pair<uint64_t, int32_t>> key(n);
+  for (int64_t v = 0; v < n; ++v) {
+    const uint32_t qx = (uint32_t)std::lround((xy[2 * v] - x0) * sc);
+    const uint32_t qy = (uint32_t)std::lround((xy[2 * v + 1] - y0) * sc);
+    key[v] = {hilbert_index(qx, qy, b), (int32_t)v};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int32_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = key[i].second;
+  return order;
+}
+
 }  // namespace
 }  // namespace fdu
 
@@ -509,6 +555,7 @@ extern "C" fdu_status fdu_prep_build(fdu_prep** out, int64_t nv_total, int64_t n
     if (nv_total >= INT32_MAX || ne >= INT32_MAX) throw Error(FDU_ERR_INVALID_ARG, "mesh too large for 32-bit ids");
     if (deg < 1 || deg > 6) throw Error(FDU_ERR_INVALID_ARG, "deg must be in 1..6");
     if (level < 0 || level > 2) throw Error(FDU_ERR_INVALID_ARG, "level must be 0, 1 or 2");
+    if (reorder < 0 || reorder > 2) throw Error(FDU_ERR_INVALID_ARG, "reorder must be 0, 1 or 2");
     if (periodic && (!(Lx > 0) || !(Ly > 0))) throw Error(FDU_ERR_INVALID_ARG, "periodic box must be positive");
     const int64_t ng = nv_total - nv_real;
     if (ng > 0 && (!ghost_src || !ghost_refl)) throw Error(FDU_ERR_INVALID_ARG, "ghost arrays required");
@@ -530,8 +577,8 @@ extern "C" fdu_status fdu_prep_build(fdu_prep** out, int64_t nv_total, int64_t n
 
     // vertex order: real vertices first (natural or RCM), ghosts after in input order
     std::vector<int32_t> perm(nv_total);
-    if (reorder == 1) {
-      std::vector<int32_t> o = rcm_order(m);
+    if (reorder == 1 || reorder == 2) {
+      std::vector<int32_t> o = reorder == 1 ? rcm_order(m) : hilbert_order(m, xy);
       std::copy(o.begin(), o.end(), perm.begin());
     } else {
       std::iota(perm.begin(), perm.begin() + nv_real, 0);

@@ -73,8 +73,18 @@ struct fdu_solver {
   DevBuf<double> geo, wfg, we, cO, hmin, flux, part;
   DevBuf<float> geo32, wfg32, we32;
   int cfl_blocks = 0;
+  // live kernel timer (fdu_kernel_timer_start/stop): event pairs recorded
+  // around each launch of the ghost, edge, vertex and CFL kernels
+  bool timer_on = false;
+  int timer_cap = 0;
+  int timer_n[4] = {0, 0, 0, 0};
+  std::vector<hipEvent_t> timer_ev[4];
+  ~fdu_solver() {
+    for (auto& v : timer_ev)
+      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+  }
   int edge_variant = 0;    // 0: k_edge_flux, 1: k_edge_flux_lean
-  int vertex_variant = 0;  // 0: k_vertex (16 lanes, loops), 1-3: k_vertex_pipe with 16, 32, 8 lanes
+  int vertex_variant = 0;  // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair
 };
 
 namespace {
@@ -131,16 +141,38 @@ inline unsigned nblocks(int64_t nthreads) { return (unsigned)((nthreads + 255) /
 
 void launch_check() { FDU_HIP(hipGetLastError()); }
 
+// Records a start/stop event pair around `launch` when the solver's live timer
+// is on and has room (never while the stream is being captured).
+template <class F>
+void timed_launch(fdu_solver* s, int phase, hipStream_t st, F&& launch) {
+  bool rec = s->timer_on && s->timer_n[phase] < s->timer_cap;
+  if (rec) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    FDU_HIP(hipStreamIsCapturing(st, &cs));
+    rec = cs == hipStreamCaptureStatusNone;
+  }
+  if (!rec) {
+    launch();
+    return;
+  }
+  const int i = s->timer_n[phase]++;
+  FDU_HIP(hipEventRecord(s->timer_ev[phase][2 * i], st));
+  launch();
+  FDU_HIP(hipEventRecord(s->timer_ev[phase][2 * i + 1], st));
+}
+
 template <class T>
 void fill_ghosts_t(fdu_solver* s, T* w, hipStream_t st) {
   if (s->ng == 0) return;
-  hipLaunchKernelGGL(k_fill_ghosts<T>, dim3(nblocks(s->ng)), dim3(256), 0, st, w, (int)s->nv_real, (int)s->ng,
-                     s->gsrc.p, reinterpret_cast<const signed char*>(s->grefl.p));
+  timed_launch(s, 0, st, [&] {
+    hipLaunchKernelGGL(k_fill_ghosts<T>, dim3(nblocks(s->ng)), dim3(256), 0, st, w, (int)s->nv_real, (int)s->ng,
+                       s->gsrc.p, reinterpret_cast<const signed char*>(s->grefl.p));
+  });
   launch_check();
 }
 
 constexpr int kEdgeVariants = 2;
-constexpr int kVertexVariants = 8;
+constexpr int kVertexVariants = 10;
 
 template <class T, class TG>
 void edge_flux_launch(fdu_solver* s, const T* w, const TG* geo, double* r, hipStream_t st) {
@@ -155,10 +187,12 @@ void edge_flux_launch(fdu_solver* s, const T* w, const TG* geo, double* r, hipSt
 template <class T>
 void edge_flux_t(fdu_solver* s, const T* w, double* r, hipStream_t st) {
   if (s->ne_flux == 0) return;
-  if (s->prec == FDU_F64)
-    edge_flux_launch<T, double>(s, w, s->geo.p, r, st);
-  else
-    edge_flux_launch<T, float>(s, w, s->geo32.p, r, st);
+  timed_launch(s, 1, st, [&] {
+    if (s->prec == FDU_F64)
+      edge_flux_launch<T, double>(s, w, s->geo.p, r, st);
+    else
+      edge_flux_launch<T, float>(s, w, s->geo32.p, r, st);
+  });
   launch_check();
 }
 
@@ -167,6 +201,15 @@ void vertex_pipe_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, 
                         double a, double b, const double* dt, hipStream_t st) {
   const unsigned nb = nblocks(s->nv_real * LPV);
   hipLaunchKernelGGL((k_vertex_pipe<T, TW, LPV, MV, ME>), dim3(nb), dim3(256), 0, st, w, s->vptr.p, s->vcol.p, wfg,
+                     s->eptr.p, s->ecol.p, we, s->cO.p, s->flux.p, (int)s->nv_real, s->params.gamma - 1.0, mode, R,
+                     wn, out, a, b, dt);
+}
+
+template <class T, class TW, int LPV, int MV, int ME>
+void vertex_pair_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
+                        double a, double b, const double* dt, hipStream_t st) {
+  const unsigned nb = nblocks(s->nv_real * LPV);
+  hipLaunchKernelGGL((k_vertex_pair<T, TW, LPV, MV, ME>), dim3(nb), dim3(256), 0, st, w, s->vptr.p, s->vcol.p, wfg,
                      s->eptr.p, s->ecol.p, we, s->cO.p, s->flux.p, (int)s->nv_real, s->params.gamma - 1.0, mode, R,
                      wn, out, a, b, dt);
 }
@@ -191,6 +234,8 @@ void vertex_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int m
     case 5: vertex_loop_launch<T, TW, 4, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
     case 6: vertex_loop_launch<T, TW, 16, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
     case 7: vertex_loop_launch<T, TW, 8, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 8: vertex_pair_launch<T, TW, 16, 3, 6>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 9: vertex_pair_launch<T, TW, 8, 5, 11>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
     default: vertex_loop_launch<T, TW, 16, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st);
   }
 }
@@ -198,19 +243,23 @@ void vertex_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int m
 template <class T>
 void vertex_t(fdu_solver* s, const T* w, int mode, T* R, const T* wn, T* out, double a, double b, const double* dt,
               hipStream_t st) {
-  if (s->prec == FDU_F64)
-    vertex_launch<T, double>(s, w, s->wfg.p, s->we.p, mode, R, wn, out, a, b, dt, st);
-  else
-    vertex_launch<T, float>(s, w, s->wfg32.p, s->we32.p, mode, R, wn, out, a, b, dt, st);
+  timed_launch(s, 2, st, [&] {
+    if (s->prec == FDU_F64)
+      vertex_launch<T, double>(s, w, s->wfg.p, s->we.p, mode, R, wn, out, a, b, dt, st);
+    else
+      vertex_launch<T, float>(s, w, s->wfg32.p, s->we32.p, mode, R, wn, out, a, b, dt, st);
+  });
   launch_check();
 }
 
 template <class T>
 void cfl_t(fdu_solver* s, const T* w, double cfl, double* dt, hipStream_t st) {
-  hipLaunchKernelGGL(k_cfl_partial<T>, dim3(s->cfl_blocks), dim3(256), 0, st, w, s->hmin.p, (int)s->nv_real,
-                     s->params.gamma, s->part.p);
-  launch_check();
-  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, st, s->part.p, s->cfl_blocks, cfl, dt);
+  timed_launch(s, 3, st, [&] {
+    hipLaunchKernelGGL(k_cfl_partial<T>, dim3(s->cfl_blocks), dim3(256), 0, st, w, s->hmin.p, (int)s->nv_real,
+                       s->params.gamma, s->part.p);
+    launch_check();
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, st, s->part.p, s->cfl_blocks, cfl, dt);
+  });
   launch_check();
 }
 
@@ -1037,6 +1086,46 @@ fdu_status fdu_kernel_times(fdu_solver* s, void* w, void* scratch, int reps, dou
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+  });
+}
+
+fdu_status fdu_kernel_timer_start(fdu_solver* s, int capacity) {
+  return guard([&] {
+    ready(s);
+    need(capacity > 0 && capacity <= (1 << 20), "capacity must be in [1, 2^20]");
+    DeviceGuard dg(s->device);
+    for (auto& v : s->timer_ev) {
+      while ((int)v.size() < 2 * capacity) {
+        hipEvent_t e;
+        FDU_HIP(hipEventCreate(&e));
+        v.push_back(e);
+      }
+    }
+    s->timer_cap = capacity;
+    for (int& n : s->timer_n) n = 0;
+    s->timer_on = true;
+  });
+}
+
+fdu_status fdu_kernel_timer_stop(fdu_solver* s, double* avg_ms, int* counts) {
+  return guard([&] {
+    if (!s) throw Error(FDU_ERR_INVALID_ARG, "NULL solver");
+    need(avg_ms && counts, "invalid argument");
+    need(s->timer_on, "kernel timer not started");
+    DeviceGuard dg(s->device);
+    s->timer_on = false;
+    for (int ph = 0; ph < 4; ++ph) {
+      const int n = s->timer_n[ph];
+      double sum = 0.0;
+      if (n > 0) FDU_HIP(hipEventSynchronize(s->timer_ev[ph][2 * n - 1]));
+      for (int i = 0; i < n; ++i) {
+        float ms = 0.f;
+        FDU_HIP(hipEventElapsedTime(&ms, s->timer_ev[ph][2 * i], s->timer_ev[ph][2 * i + 1]));
+        sum += ms;
+      }
+      counts[ph] = n;
+      avg_ms[ph] = n > 0 ? sum / n : 0.0;
+    }
   });
 }
 

@@ -62,6 +62,8 @@ _SIGS = {
     "fdu_rk_stage": (I32, [VP, I32, VP, VP, VP, VP, VP]),
     "fdu_rk_step": (I32, [VP, VP, VP, D, VP, VP]),
     "fdu_kernel_times": (I32, [VP, VP, VP, I32, VP, VP]),
+    "fdu_kernel_timer_start": (I32, [VP, I32]),
+    "fdu_kernel_timer_stop": (I32, [VP, VP, VP]),
     "fdu_enable_adjoint": (I32, [VP]),
     "fdu_set_variants": (I32, [VP, I32, I32]),
     "fdu_get_variants": (I32, [VP, P(I32), P(I32), P(I32), P(I32)]),
@@ -313,6 +315,18 @@ class Solver:
         _call("fdu_kernel_times", self.handle, self._state(w), C.c_void_p(scratch.data_ptr()), int(reps), out,
               _stream())
         return dict(ghost=out[0], edge=out[1], vertex=out[2], cfl=out[3])
+
+    def kernel_timer_start(self, capacity: int = 4096):
+        """Bracket every later kernel launch of this solver with HIP events
+        (first `capacity` launches of each kind) on the launching stream."""
+        _call("fdu_kernel_timer_start", self.handle, int(capacity))
+
+    def kernel_timer_stop(self):
+        """Stop the live timer; returns ({kind: mean ms}, {kind: launches})."""
+        avg, cnt = (C.c_double * 4)(), (C.c_int * 4)()
+        _call("fdu_kernel_timer_stop", self.handle, avg, cnt)
+        keys = ("ghost", "edge", "vertex", "cfl")
+        return dict(zip(keys, list(avg))), dict(zip(keys, list(cnt)))
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

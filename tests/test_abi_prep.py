@@ -32,7 +32,8 @@ def test_every_declared_symbol_is_exported():
 
 
 CASES = [(33, True, 0, 3, 1), (33, True, 0, 5, 1), (18, False, 4, 5, 0), (18, False, 4, 5, 1),
-         (65, False, 4, 5, 1)]   # 65^2 seed 3 and 0: mirror-ghost corners with rank-deficient systems
+         (65, False, 4, 5, 1),   # 65^2 seed 3 and 0: mirror-ghost corners with rank-deficient systems
+         (33, True, 0, 5, 2), (18, False, 4, 5, 2)]   # Hilbert order
 
 
 @pytest.mark.parametrize("N,periodic,ghosts,deg,reorder", CASES)
@@ -71,6 +72,18 @@ def test_prep_matches_oracle(N, periodic, ghosts, deg, reorder):
         assert err <= 1e-12 * scale, (i, err / scale)
     if ghosts:
         np.testing.assert_array_equal(perm[A["ghost_src"]], m.ghost_src)
+
+
+def test_hilbert_order_is_local():
+    """Hilbert numbering: consecutive real vertices are mesh neighbours far more
+    often than in a random order, and every 64-vertex run is a compact patch."""
+    m = make_mesh(64, L=1.0, periodic=True, seed=5, jitter=0.0)
+    perm = fdu.Prep(m, deg=3, reorder=2).arrays()["perm"][:m.nv_real]
+    i, j = perm // 64, perm % 64
+    steps = np.abs(np.diff(i)) + np.abs(np.diff(j))
+    assert np.mean(steps == 1) > 0.95
+    for b in range(0, m.nv_real, 64):
+        assert np.ptp(i[b:b + 64]) <= 8 and np.ptp(j[b:b + 64]) <= 8
 
 
 @pytest.mark.parametrize("N,diag", [(65, "random"), (33, "uniform")])

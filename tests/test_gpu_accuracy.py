@@ -5,11 +5,13 @@ two-level stencils): L2 density error against the exact solution and its
 observed order.
 
 On the paper's regular diagonalized meshes (Sec. 3.1) the runs must finish and
-converge.  On jittered meshes (uniform or random diagonals) the table is only
-reported: the truncation error does not converge there (Sec. 3.1, general
+converge at close to fourth order over 65^2 -> 257^2 (measured 4.0 and
+4.1-4.4); at 513^2 the error (3e-8) flattens.  On jittered meshes (uniform or
+random diagonals) the table is only reported: the truncation error does not converge there (Sec. 3.1, general
 meshes) and the runs diverge before t = 2 from 129^2-257^2 on (growing modes of
-the semi-discrete operator).  Where both precisions finish,
-FP32-storage errors must be within 1e-3 of the FP64 ones."""
+the semi-discrete operator).  Where both precisions finish, FP32-storage errors
+must be within 1e-3 of the FP64 ones plus the FP32 rounding floor (5e-6: one
+rounding of O(1) values per stage, accumulated over up to ~1500 stages)."""
 import json
 
 import numpy as np
@@ -76,7 +78,7 @@ def test_vortex_t2_accuracy():
         if r["mesh"] == "regular":
             assert r["L2_rho_f64"] is not None and r["L2_rho_f32"] is not None, r
         if r["L2_rho_f64"] is not None and r["L2_rho_f32"] is not None:
-            assert abs(r["L2_rho_f32"] - r["L2_rho_f64"]) <= 1e-3 * r["L2_rho_f64"] + 1e-7, r
+            assert abs(r["L2_rho_f32"] - r["L2_rho_f64"]) <= 1e-3 * r["L2_rho_f64"] + 5e-6, r
     for deg in (3, 5):
         e = [r["L2_rho_f64"] for r in table if r["mesh"] == "regular" and r["deg"] == deg]
-        assert np.log(e[1] / e[3]) / np.log(4.0) > 2.0, e
+        assert np.log2(e[0] / e[1]) > 3.5 and np.log2(e[1] / e[2]) > 3.5, e

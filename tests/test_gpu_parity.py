@@ -238,7 +238,7 @@ def test_full_size_sod_sampled():
     assert err1.max() <= 1e-14
 
 
-@pytest.mark.parametrize("edge,vertex", [(e, v) for e in range(2) for v in range(8)])
+@pytest.mark.parametrize("edge,vertex", [(e, v) for e in range(2) for v in range(10)])
 def test_kernel_variants(vortex33_p5, sod24_p5, edge, vertex):
     """Every kernel variant computes the same residual (to the parity bar)."""
     for c in (vortex33_p5, sod24_p5):
@@ -267,3 +267,25 @@ def test_autotune_picks_a_variant(vortex33_p5):
     err = _residual_err(c)
     c.s.set_variants(0, 0)
     assert err.max() <= TOL
+
+
+def test_live_kernel_timer(sod24_p5):
+    """The live timer counts every launch of one SSP-RK3 step (CFL reduction +
+    3 x ghost fill, edge flux, vertex step), leaves the results unchanged, and
+    refuses a stop without a start."""
+    fdu = _fdu()
+    c = sod24_p5
+    w_a, w_b = c.w_dev(), c.w_dev()
+    scr_a, scr_b = torch.empty(2 * c.m.nv, 4, dtype=torch.float64, device="cuda"), \
+        torch.empty(2 * c.m.nv, 4, dtype=torch.float64, device="cuda")
+    dt_a, dt_b = torch.empty(1, dtype=torch.float64, device="cuda"), torch.empty(1, dtype=torch.float64, device="cuda")
+    c.s.rk_step(w_a, scr_a, dt_a, cfl=0.2)
+    c.s.kernel_timer_start(capacity=16)
+    c.s.rk_step(w_b, scr_b, dt_b, cfl=0.2)
+    avg, cnt = c.s.kernel_timer_stop()
+    assert cnt == dict(ghost=3, edge=3, vertex=3, cfl=1), cnt
+    assert all(0.0 < avg[k] < 100.0 for k in cnt), avg
+    assert torch.equal(w_a, w_b)
+    c.s.rk_step(w_b, scr_b, dt_b, cfl=0.2)          # timer off again: nothing recorded, no error
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        c.s.kernel_timer_stop()

@@ -24,8 +24,10 @@ def exe(tmp_path_factory):
     return out
 
 
-@pytest.mark.parametrize("positivity,power,tol", [(1, 1, 1e-7), (0, 1, 1e-7), (1, 2, 1e-6)])
-def test_edge_vjp_matches_finite_differences(exe, positivity, power, tol):
-    r = subprocess.run([exe, str(tol), str(positivity), str(power), "1e-6"], capture_output=True, text=True)
+@pytest.mark.parametrize("positivity,power,riemann,tol", [(1, 1, 0, 1e-7), (0, 1, 0, 1e-7), (1, 2, 0, 1e-6),
+                                                          (1, 1, 1, 2e-5)])
+def test_edge_vjp_matches_finite_differences(exe, positivity, power, riemann, tol):
+    r = subprocess.run([exe, str(tol), str(positivity), str(power), "1e-6", str(riemann)], capture_output=True,
+                       text=True)
     print(r.stdout)
     assert r.returncode == 0, r.stdout
