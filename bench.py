@@ -34,20 +34,34 @@ SOD_CFL = 0.2
 METRIC = "vertex-stage updates/sec + HBM GB/s vs peak; batched & adjoint vs plain path"
 
 
-def kernel_bytes(A, precision_bytes=8):
+def kernel_bytes(A, precision_bytes=8, blocks=None):
     """Algorithmic bytes per launch (each datum counted once).
     edge:   per flux edge 6 int32 ids + 6 geometry values + 4 flux values written,
             plus every state row read once;
     vertex: per real vertex two CSR pointers, c_O (2), w_n (4) and the output (4),
             per vertex entry an int32 id + 2 weights, per edge entry an int32 id +
-            1 weight, plus every state row and every flux row read once."""
+            1 weight, plus every state row and every flux row read once.
+            LDS-staged variants (blocks given): 16-bit ids instead, plus per block
+            3 int32 pointers and its int32 row lists (the row data itself still
+            counted once)."""
     s = precision_bytes
     nvt, nvr, nef, nzv, nze = A["nv_total"], A["nv_real"], A["ne_flux"], A["nnz_v"], A["nnz_e"]
     edge = nef * (6 * 4 + 6 * s + 4 * 8) + nvt * 4 * s
-    vertex = nvr * (2 * 4 + 2 * 8 + 4 * s + 4 * s) + nzv * (4 + 2 * s) + nze * (4 + s) + nvt * 4 * s + nef * 4 * 8
+    ids = 4 if blocks is None else 2
+    vertex = nvr * (2 * 4 + 2 * 8 + 4 * s + 4 * s) + nzv * (ids + 2 * s) + nze * (ids + s) + nvt * 4 * s + nef * 4 * 8
+    if blocks is not None:
+        vertex += blocks["n_blocks"] * 3 * 4 + blocks["halo_rows"] * 4
     return dict(edge=edge, vertex=vertex)
 
 
+# kernel (template instance) behind each variant number of the library
+EDGE_KERNELS = {0: "k_edge_flux<double, double>", 1: "k_edge_flux_lean<double, double>"}
+VERTEX_KERNELS = {0: "k_vertex<double, double, 16, false>", 1: "k_vertex_pipe<double, double, 16, 2, 3>",
+                  2: "k_vertex_pipe<double, double, 32, 1, 2>", 3: "k_vertex_pipe<double, double, 8, 3, 6>",
+                  4: "k_vertex<double, double, 8, false>", 5: "k_vertex<double, double, 4, false>",
+                  6: "k_vertex<double, double, 16, true>", 7: "k_vertex<double, double, 8, true>",
+                  8: "k_vertex_pair<double, double, 16, 3, 6>", 9: "k_vertex_pair<double, double, 8, 5, 11>",
+                  10: "k_vertex_lds<double, double, 8, 3, 6, 1, 5>", 11: "k_vertex_lds<double, double, 4, 5, 11, 1, 4>"}
 KERNEL_SOURCES = ("csrc/kernels.hpp", "csrc/batch.hpp", "csrc/adjoint.hpp", "csrc/runtime.hip", "build.py")
 
 
@@ -60,7 +74,7 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel, N):
+def traffic_from_profiles(kernel, N, reorder):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
@@ -68,7 +82,7 @@ def traffic_from_profiles(kernel, N):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("source_hash") != source_hash() or d.get("N") != N:
+    if d.get("source_hash") != source_hash() or d.get("N") != N or d.get("reorder") != reorder:
         return None
     k = d.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
@@ -121,7 +135,7 @@ def bench_batched(n_inst, steps, cfl, edge_variant, vertex_variant, log):
     solvers, w0s = [], []
     for i, sp in enumerate(specs):
         m = make_mesh(sp["N"], L=10.0, periodic=True, seed=sp["seed"])
-        prep = fdu.Prep(m, deg=5, reorder=1)
+        prep = fdu.Prep(m, deg=5, reorder=2)
         perm = prep.arrays()["perm"]
         s = fdu.Solver(prep, device=0)
         s.set_variants(edge_variant, vertex_variant)       # used by the per-instance schedule
@@ -185,7 +199,7 @@ def bench_adjoint(N, nsteps, ckpt, log):
     from paper_2102_12933_amd.inputs import make_mesh, vertex_areas, vortex_state
 
     m = make_mesh(N, L=10.0, periodic=True, seed=0)
-    prep = fdu.Prep(m, deg=5, reorder=1)
+    prep = fdu.Prep(m, deg=5, reorder=2)
     perm = prep.arrays()["perm"]
     s = fdu.Solver(prep, device=0, weno_eps=1e-6)
     s.enable_adjoint()
@@ -236,7 +250,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--N", type=int, default=1025)
-    ap.add_argument("--reorder", type=int, default=1)
+    ap.add_argument("--reorder", type=int, default=2, help="0 natural, 1 RCM, 2 Hilbert (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=30)
     ap.add_argument("--cfl", type=float, default=SOD_CFL)
@@ -307,15 +321,15 @@ def main():
         raise RuntimeError("non-physical state after a step")
     log(f"timed {args.steps} steps: {el * 1e3:.2f} ms; live kernel means (ms) {kt}, launches {kcount}")
 
-    nb = kernel_bytes(A)
+    blocks = solver.vertex_block_info() if tune["vertex"] in (10, 11) else None
+    nb = kernel_bytes(A, blocks=blocks)
     kern = {}
     for k in ("edge", "vertex"):
         ms = kt[k]
         kern[k] = dict(avg_ms=ms, launches=kcount[k], bytes=nb[k], gbs=nb[k] / (ms * 1e-3) / 1e9)
     dom = max(("edge", "vertex"), key=lambda k: kt[k])
-    names = dict(edge=["k_edge_flux", "k_edge_flux_lean"][tune["edge"]],
-                 vertex="k_vertex_pipe" if tune["vertex"] in (1, 2, 3) else "k_vertex")
-    traffic = traffic_from_profiles(names[dom], args.N)
+    names = dict(edge=EDGE_KERNELS[tune["edge"]], vertex=VERTEX_KERNELS[tune["vertex"]])
+    traffic = traffic_from_profiles(names[dom], args.N, args.reorder)
     achieved = kern[dom]["gbs"]
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
@@ -344,6 +358,7 @@ def main():
         "roofline": roofline,
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in d.items()}
                     for k, d in kern.items()} | {"ghost_ms": round(kt["ghost"], 5), "cfl_ms": round(kt["cfl"], 5)},
+        "vertex_blocks": blocks,
         "autotune": {"edge_variant": tune["edge"], "vertex_variant": tune["vertex"],
                      "edge_ms": [round(t, 5) for t in tune["edge_ms"]],
                      "vertex_ms": [round(t, 5) for t in tune["vertex_ms"]]},

@@ -297,12 +297,22 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
  *           loops with 16 and 8 lanes and non-temporal stencil-array loads;
  *           8, 9 = 16 and 8 lanes per vertex in pairs, each lane of a pair
  *           gathering one 16-byte half of a stencil row (half the gather
- *           instructions), all loads issued before the arithmetic.
+ *           instructions), all loads issued before the arithmetic;
+ *           10, 11 = 8 and 4 lanes per vertex over vertex blocks whose
+ *           stencil halo (state and flux rows) is first staged in LDS, 16-bit
+ *           block-local row indices (blocks are built at fdu_finalize; they
+ *           are compact when the prep used the Hilbert order, reorder = 2).
  * fdu_set_variants / fdu_get_variants select and report them (n_edge, n_vertex:
  * how many exist).  fdu_autotune times every edge variant and then every vertex
  * variant on the given state with fdu_kernel_times (reps launches each),
  * writes the mean times (ms) to times_ms[0 .. n_edge + n_vertex - 1] and keeps
  * the fastest of each; synchronous; w and scratch as for fdu_kernel_times. */
+/* fdu_vertex_block_info: the vertex blocks built at fdu_finalize for the
+ * LDS-staged vertex variants: their number, the total length of their row
+ * lists (state rows + flux rows, with repeats across blocks) and the largest
+ * list of one block (each row takes 32 bytes of LDS).  Any pointer may be
+ * NULL.  FDU_ERR_STATE before fdu_finalize. */
+fdu_status fdu_vertex_block_info(const fdu_solver* s, int* n_blocks, int64_t* halo_rows, int* rows_max);
 fdu_status fdu_set_variants(fdu_solver* s, int edge_variant, int vertex_variant);
 fdu_status fdu_get_variants(const fdu_solver* s, int* edge_variant, int* vertex_variant, int* n_edge, int* n_vertex);
 fdu_status fdu_autotune(fdu_solver* s, void* w, void* scratch, int reps, double* times_ms, void* stream);

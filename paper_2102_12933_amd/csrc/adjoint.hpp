@@ -263,26 +263,48 @@ FDU_HD void riemann_flux_T(const double wl[4], const double wr[4], double nx, do
   normal_flux_T(wr, nx, ny, S.gm1, hb, 0.0, 0.0, wrb);
 }
 
-// Cotangents Wb of the six stencil states of one edge for the flux cotangent
-// ob (the reverse of edge_flux_one).
-FDU_HD void edge_vjp_one(const double W[6][4], const double g[6], const double ob[4], const Scheme& S,
-                         double Wb[6][4]) {
+// Cotangents of the six stencil states of one edge for the flux cotangent ob
+// (the reverse of edge_flux_one).  load(s, q, again) writes stencil state s
+// to q; it is called a second time (again = true) near the end instead of
+// keeping the states live.  store(s, q) receives the cotangent of state s.
+template <class Load, class Store>
+FDU_HD void edge_vjp_one(Load&& load, const double g[6], const double ob[4], const Scheme& S, Store&& store) {
   const double nx = g[4], ny = g[5];
   // ---- forward recomputation
-  const Frame F = roe_frame<double>(W[2], W[3], nx, ny, S.gm1);
+  double W2[4], W3[4];
+  load(2, W2, false);
+  load(3, W3, false);
+  const Frame F = roe_frame<double>(W2, W3, nx, ny, S.gm1);
   double Cv[6][4];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) to_char(F, S.gm1, W[k], Cv[k]);
-  WenoGeom GL, GR;
-  weno_geom(g[0], g[1], g[2], GL);
-  weno_geom(-g[3], -g[2], -g[1], GR);
-  double cl[4], cr[4];
+  for (int k = 0; k < 6; ++k) {
+    double q[4];
+    if (k == 2 || k == 3) {
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const double ul[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
-    const double ur[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
-    cl[c] = weno_eval(GL, ul, S.eps, S.power);
-    cr[c] = weno_eval(GR, ur, S.eps, S.power);
+      for (int i = 0; i < 4; ++i) q[i] = k == 2 ? W2[i] : W3[i];
+    } else {
+      load(k, q, false);
+    }
+    to_char(F, S.gm1, q, Cv[k]);
+  }
+  double cl[4], cr[4];
+  {
+    WenoGeom G;
+    weno_geom(g[0], g[1], g[2], G);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double u[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
+      cl[c] = weno_eval(G, u, S.eps, S.power);
+    }
+  }
+  {
+    WenoGeom G;
+    weno_geom(-g[3], -g[2], -g[1], G);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double u[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
+      cr[c] = weno_eval(G, u, S.eps, S.power);
+    }
   }
   double wl[4], wr[4];
   from_char(F, cl, wl);
@@ -293,61 +315,91 @@ FDU_HD void edge_vjp_one(const double W[6][4], const double g[6], const double o
     fr = !physical(wr, S.gm1);
     if (fl)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) wl[k] = W[2][k];
+      for (int k = 0; k < 4; ++k) wl[k] = W2[k];
     if (fr)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) wr[k] = W[3][k];
+      for (int k = 0; k < 4; ++k) wr[k] = W3[k];
   }
 
   // ---- Riemann flux
   double wlb[4], wrb[4];
   riemann_flux_T(wl, wr, nx, ny, S, ob, wlb, wrb);
-#pragma unroll
-  for (int s = 0; s < 6; ++s)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) Wb[s][k] = 0.0;
   // ---- back-projection (or the fallback's copy of the end state)
   FrameBar Fb;
   double clb[4] = {0.0, 0.0, 0.0, 0.0}, crb[4] = {0.0, 0.0, 0.0, 0.0};
+  double e2[4] = {0.0, 0.0, 0.0, 0.0}, e3[4] = {0.0, 0.0, 0.0, 0.0};   // direct cotangents of W2, W3
   if (fl) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Wb[2][k] += wlb[k];
+    for (int k = 0; k < 4; ++k) e2[k] = wlb[k];
   } else {
     from_char_T(F, wlb, clb);
     from_char_frame_T(F, cl, wlb, Fb);
   }
   if (fr) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Wb[3][k] += wrb[k];
+    for (int k = 0; k < 4; ++k) e3[k] = wrb[k];
   } else {
     from_char_T(F, wrb, crb);
     from_char_frame_T(F, cr, wrb, Fb);
   }
-  // ---- NU-WENO5 along the stencil, one characteristic component at a time
+  // ---- NU-WENO5 along the stencil, one side at a time (geometry recomputed)
   double Cb[6][4];
 #pragma unroll
   for (int s = 0; s < 6; ++s)
 #pragma unroll
     for (int k = 0; k < 4; ++k) Cb[s][k] = 0.0;
+  {
+    WenoGeom G;
+    weno_geom(opaque(g[0]), opaque(g[1]), opaque(g[2]), G);
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const double ul[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
-    const double ur[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
-    double ubl[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, ubr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    weno_eval_T(GL, ul, S.eps, S.power, clb[c], ubl);
-    weno_eval_T(GR, ur, S.eps, S.power, crb[c], ubr);
+    for (int c = 0; c < 4; ++c) {
+      const double u[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
+      double ub[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      weno_eval_T(G, u, S.eps, S.power, clb[c], ub);
 #pragma unroll
-    for (int m = 0; m < 5; ++m) Cb[m][c] += ubl[m];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) Cb[5 - m][c] += ubr[m];
+      for (int m = 0; m < 5; ++m) Cb[m][c] += ub[m];
+    }
   }
-  // ---- characteristic projection: states at the fixed frame, then the frame
+  {
+    WenoGeom G;
+    weno_geom(-opaque(g[3]), -opaque(g[2]), -opaque(g[1]), G);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double u[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
+      double ub[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      weno_eval_T(G, u, S.eps, S.power, crb[c], ub);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) Cb[5 - m][c] += ub[m];
+    }
+  }
+  // ---- characteristic projection: frame cotangents first (they need the
+  // states, loaded again), then the states at the fixed frame
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
-    to_char_T_acc(F, S.gm1, Cb[s], Wb[s]);
-    to_char_frame_T(F, S.gm1, W[s], Cb[s], Fb);
+    double q[4];
+    load(s, q, true);
+    to_char_frame_T(F, S.gm1, q, Cb[s], Fb);
   }
-  roe_frame_T(F, W[2], W[3], S.gm1, Fb, Wb[2], Wb[3]);
+  {
+    double q2[4], q3[4];
+    load(2, q2, true);
+    load(3, q3, true);
+    roe_frame_T(F, q2, q3, S.gm1, Fb, e2, e3);
+  }
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    double wb[4] = {0.0, 0.0, 0.0, 0.0};
+    if (s == 2) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wb[k] = e2[k];
+    }
+    if (s == 3) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wb[k] = e3[k];
+    }
+    to_char_T_acc(F, S.gm1, Cb[s], wb);
+    store(s, wb);
+  }
 }
 
 // rbar_k = -sum_{O uses k} we_Ok Rbar_O (transposed edge CSR)
@@ -372,7 +424,7 @@ __global__ void __launch_bounds__(256) k_edge_cot(const int* __restrict__ tptr, 
 
 // Per flux edge: cotangents of its six stencil states, slots[e][s][4].
 template <class T, class TG>
-__global__ void __launch_bounds__(256) k_edge_vjp(const T* __restrict__ w, const int* __restrict__ sten,
+__global__ void __launch_bounds__(256, 2) k_edge_vjp(const T* __restrict__ w, const int* __restrict__ sten,
                                                   const TG* __restrict__ geo, const double* __restrict__ rbar,
                                                   double* __restrict__ slots, int ne, Scheme S) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -380,22 +432,19 @@ __global__ void __launch_bounds__(256) k_edge_vjp(const T* __restrict__ w, const
   int id[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) id[k] = sten[6 * (size_t)e + k];
-  double W[6][4];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) load4(w, id[k], W[k]);
   double g[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = (double)geo[6 * (size_t)e + k];
   double ob[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) ob[k] = rbar[4 * (size_t)e + k];
-  double Wb[6][4];
-  edge_vjp_one(W, g, ob, S, Wb);
   double* out = slots + 24 * (size_t)e;
-#pragma unroll
-  for (int s = 0; s < 6; ++s)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) out[4 * s + k] = Wb[s][k];
+  edge_vjp_one([&](int s, double q[4], bool again) { load4(w, again ? opaque(id[s]) : id[s], q); }, g, ob, S,
+               [&](int s, const double q[4]) {
+                 double2* o = reinterpret_cast<double2*>(out + 4 * s);
+                 o[0] = make_double2(q[0], q[1]);
+                 o[1] = make_double2(q[2], q[3]);
+               });
 }
 
 // Per vertex (real and ghost): flux-cotangent gathers over the transposed

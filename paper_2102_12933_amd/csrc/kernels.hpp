@@ -60,6 +60,22 @@ __device__ __forceinline__ double frcp(double x) {
   return r;
 }
 
+// Opaque copy of a value: the compiler cannot merge a computation on it with
+// an earlier identical one, so recomputing (cheap) replaces keeping the
+// earlier result live across the whole reverse sweep (registers).
+FDU_HD double opaque(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(x));
+#endif
+  return x;
+}
+FDU_HD int opaque(int x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(x));
+#endif
+  return x;
+}
+
 // ----------------------------------------------------------------------------
 // Non-uniform WENO5 midpoint interpolation (Appendix).  Coordinates are
 // normalised by the middle-edge length, so x2 = -1/2 and x3 = +1/2 exactly and
@@ -864,6 +880,179 @@ __global__ void __launch_bounds__(256) k_vertex_pair(const T* __restrict__ w, co
   const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   vertex_pair_item<T, TW, LPV, MV, ME>(w, vptr, vcol, wfg, eptr, ecol, we, cO, r, nreal, gm1, mode, R, wn, out, a, b,
                                        dt_dev, t / LPV, t % LPV);
+}
+
+// Vertex step with the stencil halo staged in LDS.  The real vertices are cut
+// (at set-up) into blocks of consecutive ids; for each block the sorted list of
+// state rows and of flux rows its stencils read is stored with the block, and
+// the stencil entries hold 16-bit positions in those lists.  A workgroup copies
+// its block's rows into LDS (sorted ids: mostly contiguous loads, each row
+// fetched once per block instead of once per stencil entry), then walks the
+// block's vertices in rounds of 256 / LPV, LPV lanes per vertex, reading rows
+// from LDS.  The stream loads (CSR pointers, local indices, weights) of the
+// first round are issued before the staging barrier; with PF = 2 those of
+// round r + 1 are issued before round r is computed.  WPE is the occupancy
+// (waves per SIMD) the register allocation is held to.
+template <class TW, int MV, int ME>
+struct VertexFetch {
+  int v, pb, pe, qb, qe;
+  int jv[MV], ke[ME];
+  double wf[MV], wg[MV], cw[ME];
+};
+
+template <class TW, int LPV, int MV, int ME>
+__device__ __forceinline__ void vertex_fetch(VertexFetch<TW, MV, ME>& F, int v, int v1, int lane,
+                                             const int* __restrict__ vptr, const unsigned short* __restrict__ lvcol,
+                                             const TW* __restrict__ wfg, const int* __restrict__ eptr,
+                                             const unsigned short* __restrict__ lecol, const TW* __restrict__ we) {
+  F.v = v;
+  F.pb = F.pe = F.qb = F.qe = 0;
+  if (v < v1) {
+    F.pb = vptr[v]; F.pe = vptr[v + 1];
+    F.qb = eptr[v]; F.qe = eptr[v + 1];
+  }
+#pragma unroll
+  for (int s = 0; s < MV; ++s) {
+    const int p = F.pb + lane + s * LPV;
+    F.jv[s] = p < F.pe ? (int)lvcol[p] : -1;
+    F.wf[s] = p < F.pe ? (double)wfg[2 * (size_t)p] : 0.0;
+    F.wg[s] = p < F.pe ? (double)wfg[2 * (size_t)p + 1] : 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < ME; ++s) {
+    const int p = F.qb + lane + s * LPV;
+    F.ke[s] = p < F.qe ? (int)lecol[p] : -1;
+    F.cw[s] = p < F.qe ? (double)we[p] : 0.0;
+  }
+}
+
+template <class T, class TW, int LPV, int MV, int ME>
+__device__ __forceinline__ void vertex_lds_compute(const VertexFetch<TW, MV, ME>& F, int v0, int v1, int lane,
+                                                   const double* __restrict__ Lv, const double* __restrict__ Le,
+                                                   const T* __restrict__ w, const unsigned short* __restrict__ lvcol,
+                                                   const TW* __restrict__ wfg, const unsigned short* __restrict__ lecol,
+                                                   const TW* __restrict__ we, const double* __restrict__ cO, double gm1,
+                                                   int mode, T* __restrict__ R, const T* __restrict__ wn,
+                                                   T* __restrict__ out, double a, double b,
+                                                   const double* __restrict__ dt_dev) {
+  const int v = F.v;
+  const bool active = v < v1;
+  const int vv = active ? v : v0;
+  double q0[4], f0[4], g0[4];
+  load4(w, vv, q0);
+  euler_fg(q0, gm1, f0, g0);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < MV; ++s) {
+    if (F.jv[s] >= 0) {
+      const double2* lp = reinterpret_cast<const double2*>(Lv + 4 * F.jv[s]);
+      const double2 x = lp[0], y = lp[1];
+      const double q[4] = {x.x, x.y, y.x, y.y};
+      double f[4], g[4];
+      euler_fg(q, gm1, f, g);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] += F.wf[s] * (f[k] - f0[k]) + F.wg[s] * (g[k] - g0[k]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < ME; ++s) {
+    if (F.ke[s] >= 0) {
+      const double2* lp = reinterpret_cast<const double2*>(Le + 4 * F.ke[s]);
+      const double2 x = lp[0], y = lp[1];
+      acc[0] += F.cw[s] * x.x; acc[1] += F.cw[s] * x.y; acc[2] += F.cw[s] * y.x; acc[3] += F.cw[s] * y.y;
+    }
+  }
+  for (int p = F.pb + lane + MV * LPV; p < F.pe; p += LPV) {
+    const double2* lp = reinterpret_cast<const double2*>(Lv + 4 * (int)lvcol[p]);
+    const double2 x = lp[0], y = lp[1];
+    const double q[4] = {x.x, x.y, y.x, y.y};
+    const double af = (double)wfg[2 * (size_t)p], ag = (double)wfg[2 * (size_t)p + 1];
+    double f[4], g[4];
+    euler_fg(q, gm1, f, g);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += af * (f[k] - f0[k]) + ag * (g[k] - g0[k]);
+  }
+  for (int p = F.qb + lane + ME * LPV; p < F.qe; p += LPV) {
+    const double2* lp = reinterpret_cast<const double2*>(Le + 4 * (int)lecol[p]);
+    const double2 x = lp[0], y = lp[1];
+    const double c = (double)we[p];
+    acc[0] += c * x.x; acc[1] += c * x.y; acc[2] += c * y.x; acc[3] += c * y.y;
+  }
+#pragma unroll
+  for (int m = LPV / 2; m >= 1; m >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += __shfl_xor(acc[k], m, LPV);
+  }
+  if (active && lane == 0) {
+    const double cx = cO[2 * (size_t)v], cy = cO[2 * (size_t)v + 1];
+    double res[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) res[k] = -(acc[k] - (cx * f0[k] + cy * g0[k]));
+    if (mode == 0) {
+      store4(R, v, res);
+    } else {
+      const double dt = *dt_dev;
+      double n[4] = {0.0, 0.0, 0.0, 0.0};
+      if (a != 0.0) load4(wn, v, n);
+      double q[4];
+      load4(w, opaque(v), q);   // reloaded rather than kept live through the loops
+      double o[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) o[k] = a * n[k] + b * (q[k] + dt * res[k]);
+      store4(out, v, o);
+    }
+  }
+}
+
+template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE>
+__global__ void __launch_bounds__(256, WPE) k_vertex_lds(const T* __restrict__ w, const int* __restrict__ blk,
+                                                    const int* __restrict__ uvp, const int* __restrict__ uv,
+                                                    const int* __restrict__ uep, const int* __restrict__ ue,
+                                                    const int* __restrict__ vptr, const unsigned short* __restrict__ lvcol,
+                                                    const TW* __restrict__ wfg, const int* __restrict__ eptr,
+                                                    const unsigned short* __restrict__ lecol, const TW* __restrict__ we,
+                                                    const double* __restrict__ cO, const double* __restrict__ r,
+                                                    double gm1, int mode, T* __restrict__ R, const T* __restrict__ wn,
+                                                    T* __restrict__ out, double a, double b,
+                                                    const double* __restrict__ dt_dev) {
+  extern __shared__ double lds[];   // [rows][4]: the block's state rows, then its flux rows
+  constexpr int VPR = 256 / LPV;    // vertices per round
+  const int bk = xcd_block(blockIdx.x, gridDim.x);
+  const int v0 = blk[bk], v1 = blk[bk + 1];
+  const int a0 = uvp[bk], na = uvp[bk + 1] - a0;
+  const int e0 = uep[bk], ne = uep[bk + 1] - e0;
+  const int lane = threadIdx.x % LPV, sub = threadIdx.x / LPV;
+  VertexFetch<TW, MV, ME> F;
+  vertex_fetch<TW, LPV, MV, ME>(F, v0 + sub, v1, lane, vptr, lvcol, wfg, eptr, lecol, we);
+  for (int i = threadIdx.x; i < na; i += blockDim.x) {
+    double q[4];
+    load4(w, uv[a0 + i], q);
+    double2* d = reinterpret_cast<double2*>(lds + 4 * i);
+    d[0] = make_double2(q[0], q[1]);
+    d[1] = make_double2(q[2], q[3]);
+  }
+  for (int i = threadIdx.x; i < ne; i += blockDim.x) {
+    const double2* sp = reinterpret_cast<const double2*>(r + 4 * (size_t)ue[e0 + i]);
+    double2* d = reinterpret_cast<double2*>(lds + 4 * (na + i));
+    d[0] = sp[0];
+    d[1] = sp[1];
+  }
+  __syncthreads();
+  const double* Lv = lds;
+  const double* Le = lds + 4 * na;
+  for (int vb = v0; vb < v1; vb += VPR) {
+    if (PF == 2) {
+      VertexFetch<TW, MV, ME> G;
+      vertex_fetch<TW, LPV, MV, ME>(G, vb + VPR + sub, v1, lane, vptr, lvcol, wfg, eptr, lecol, we);
+      vertex_lds_compute<T, TW, LPV, MV, ME>(F, v0, v1, lane, Lv, Le, w, lvcol, wfg, lecol, we, cO, gm1, mode, R, wn,
+                                             out, a, b, dt_dev);
+      F = G;
+    } else {
+      if (vb > v0) vertex_fetch<TW, LPV, MV, ME>(F, vb + sub, v1, lane, vptr, lvcol, wfg, eptr, lecol, we);
+      vertex_lds_compute<T, TW, LPV, MV, ME>(F, v0, v1, lane, Lv, Le, w, lvcol, wfg, lecol, we, cO, gm1, mode, R, wn,
+                                             out, a, b, dt_dev);
+    }
+  }
 }
 
 // CFL time step: per-block minima of hmin_v / (|u_v| + c_v), then one block

@@ -73,6 +73,10 @@ struct fdu_solver {
   DevBuf<double> geo, wfg, we, cO, hmin, flux, part;
   DevBuf<float> geo32, wfg32, we32;
   int cfl_blocks = 0;
+  // vertex blocks with their stencil halos (LDS-staged vertex variants)
+  DevBuf<int32_t> vblk, vb_uvp, vb_uv, vb_uep, vb_ue;
+  DevBuf<uint16_t> vb_lvcol, vb_lecol;
+  int n_vblocks = 0, vb_rows_max = 0;
   // live kernel timer (fdu_kernel_timer_start/stop): event pairs recorded
   // around each launch of the ghost, edge, vertex and CFL kernels
   bool timer_on = false;
@@ -84,7 +88,7 @@ struct fdu_solver {
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
   }
   int edge_variant = 0;    // 0: k_edge_flux, 1: k_edge_flux_lean
-  int vertex_variant = 0;  // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair
+  int vertex_variant = 0;  // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair, 10-11: k_vertex_lds
 };
 
 namespace {
@@ -172,7 +176,7 @@ void fill_ghosts_t(fdu_solver* s, T* w, hipStream_t st) {
 }
 
 constexpr int kEdgeVariants = 2;
-constexpr int kVertexVariants = 10;
+constexpr int kVertexVariants = 12;
 
 template <class T, class TG>
 void edge_flux_launch(fdu_solver* s, const T* w, const TG* geo, double* r, hipStream_t st) {
@@ -214,6 +218,16 @@ void vertex_pair_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, 
                      wn, out, a, b, dt);
 }
 
+template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE>
+void vertex_lds_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
+                       double a, double b, const double* dt, hipStream_t st) {
+  if (s->n_vblocks == 0) return;
+  const size_t lds = (size_t)s->vb_rows_max * 4 * sizeof(double);
+  hipLaunchKernelGGL((k_vertex_lds<T, TW, LPV, MV, ME, PF, WPE>), dim3(s->n_vblocks), dim3(256), lds, st, w, s->vblk.p,
+                     s->vb_uvp.p, s->vb_uv.p, s->vb_uep.p, s->vb_ue.p, s->vptr.p, s->vb_lvcol.p, wfg, s->eptr.p,
+                     s->vb_lecol.p, we, s->cO.p, s->flux.p, s->params.gamma - 1.0, mode, R, wn, out, a, b, dt);
+}
+
 template <class T, class TW, int LPV, bool NT>
 void vertex_loop_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
                         double a, double b, const double* dt, hipStream_t st) {
@@ -236,6 +250,8 @@ void vertex_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int m
     case 7: vertex_loop_launch<T, TW, 8, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
     case 8: vertex_pair_launch<T, TW, 16, 3, 6>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
     case 9: vertex_pair_launch<T, TW, 8, 5, 11>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 10: vertex_lds_launch<T, TW, 8, 3, 6, 1, 5>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 11: vertex_lds_launch<T, TW, 4, 5, 11, 1, 4>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
     default: vertex_loop_launch<T, TW, 16, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st);
   }
 }
@@ -287,6 +303,73 @@ void rk_step_t(fdu_solver* s, T* w, T* scratch, double cfl, double* dt, hipStrea
   rk_stage_t<T>(s, 0, w, w, w1, dt, st);
   rk_stage_t<T>(s, 1, w, w1, w2, dt, st);
   rk_stage_t<T>(s, 2, w, w2, w, dt, st);
+}
+
+// Vertex blocks for the LDS-staged vertex kernels: consecutive real vertices
+// are grouped greedily (at most kBlockVertices per block) while the union of
+// the state rows and flux rows their stencils read stays within kBlockRows
+// rows (32 bytes each in LDS); each block stores its sorted row lists and every
+// stencil entry the 16-bit position of its row in its block's list.
+constexpr int kBlockVertices = 256;
+constexpr int kBlockRows = 768;
+
+void build_vertex_blocks(fdu_solver* s) {
+  const int64_t n = s->nv_real;
+  std::vector<int32_t> blk{0}, uvp{0}, uep{0}, uv, ue;
+  std::vector<uint16_t> lvcol(s->nnz_v), lecol(s->nnz_e);
+  std::vector<int32_t> mark_v(s->nv_total, -1), mark_e(s->ne_flux, -1), pos_v(s->nv_total), pos_e(s->ne_flux);
+  std::vector<int32_t> cur_v, cur_e;
+  int rows_max = 0;
+  auto close = [&](int64_t vend) {
+    const int64_t vbeg = blk.back();
+    std::sort(cur_v.begin(), cur_v.end());
+    std::sort(cur_e.begin(), cur_e.end());
+    for (size_t i = 0; i < cur_v.size(); ++i) pos_v[cur_v[i]] = (int32_t)i;
+    for (size_t i = 0; i < cur_e.size(); ++i) pos_e[cur_e[i]] = (int32_t)i;
+    for (int64_t v = vbeg; v < vend; ++v) {
+      for (int32_t p = s->h_vptr[v]; p < s->h_vptr[v + 1]; ++p) lvcol[p] = (uint16_t)pos_v[s->h_vcol[p]];
+      for (int32_t p = s->h_eptr[v]; p < s->h_eptr[v + 1]; ++p) lecol[p] = (uint16_t)pos_e[s->h_ecol[p]];
+    }
+    uv.insert(uv.end(), cur_v.begin(), cur_v.end());
+    ue.insert(ue.end(), cur_e.begin(), cur_e.end());
+    rows_max = std::max(rows_max, (int)(cur_v.size() + cur_e.size()));
+    blk.push_back((int32_t)vend);
+    uvp.push_back((int32_t)uv.size());
+    uep.push_back((int32_t)ue.size());
+    cur_v.clear();
+    cur_e.clear();
+  };
+  int32_t id = 0;   // block being filled (marks rows already in it)
+  for (int64_t v = 0; v < n; ++v) {
+    int add = 0;
+    for (int32_t p = s->h_vptr[v]; p < s->h_vptr[v + 1]; ++p) add += mark_v[s->h_vcol[p]] != id;
+    for (int32_t p = s->h_eptr[v]; p < s->h_eptr[v + 1]; ++p) add += mark_e[s->h_ecol[p]] != id;
+    const int64_t nvb = v - blk.back();
+    if (nvb > 0 && (nvb >= kBlockVertices || (int64_t)(cur_v.size() + cur_e.size()) + add > kBlockRows)) {
+      close(v);
+      ++id;
+    }
+    for (int32_t p = s->h_vptr[v]; p < s->h_vptr[v + 1]; ++p) {
+      const int32_t j = s->h_vcol[p];
+      if (mark_v[j] != id) { mark_v[j] = id; cur_v.push_back(j); }
+    }
+    for (int32_t p = s->h_eptr[v]; p < s->h_eptr[v + 1]; ++p) {
+      const int32_t k = s->h_ecol[p];
+      if (mark_e[k] != id) { mark_e[k] = id; cur_e.push_back(k); }
+    }
+    if ((int64_t)(cur_v.size() + cur_e.size()) > 65535)
+      throw Error(FDU_ERR_UNSUPPORTED, "a single vertex stencil exceeds the LDS block capacity");
+  }
+  if (n > blk.back()) close(n);
+  s->vblk.upload(blk.data(), blk.size());
+  s->vb_uvp.upload(uvp.data(), uvp.size());
+  s->vb_uv.upload(uv.data(), uv.size());
+  s->vb_uep.upload(uep.data(), uep.size());
+  s->vb_ue.upload(ue.data(), ue.size());
+  s->vb_lvcol.upload(lvcol.data(), lvcol.size());
+  s->vb_lecol.upload(lecol.data(), lecol.size());
+  s->n_vblocks = (int)blk.size() - 1;
+  s->vb_rows_max = rows_max;
 }
 
 // Transposed maps for the adjoint, built on the host from the uploaded
@@ -735,6 +818,7 @@ fdu_status fdu_finalize(fdu_solver* s) {
     s->h_cO = c;
     s->cfl_blocks = (int)std::min<int64_t>(1024, (s->nv_real + 255) / 256);
     s->part.alloc(s->cfl_blocks);
+    build_vertex_blocks(s);
     s->finalized = true;
   });
 }
@@ -748,6 +832,15 @@ fdu_status fdu_sizes(const fdu_solver* s, int64_t* nv_total, int64_t* nv_real, i
     if (ne_flux) *ne_flux = s->ne_flux;
     if (nnz_v) *nnz_v = s->nnz_v;
     if (nnz_e) *nnz_e = s->nnz_e;
+  });
+}
+
+fdu_status fdu_vertex_block_info(const fdu_solver* s, int* n_blocks, int64_t* halo_rows, int* rows_max) {
+  return guard([&] {
+    ready(s);
+    if (n_blocks) *n_blocks = s->n_vblocks;
+    if (halo_rows) *halo_rows = (int64_t)s->vb_uv.n + (int64_t)s->vb_ue.n;
+    if (rows_max) *rows_max = s->vb_rows_max;
   });
 }
 

@@ -63,6 +63,7 @@ _SIGS = {
     "fdu_rk_step": (I32, [VP, VP, VP, D, VP, VP]),
     "fdu_kernel_times": (I32, [VP, VP, VP, I32, VP, VP]),
     "fdu_kernel_timer_start": (I32, [VP, I32]),
+    "fdu_vertex_block_info": (I32, [VP, P(I32), P(I64), P(I32)]),
     "fdu_kernel_timer_stop": (I32, [VP, VP, VP]),
     "fdu_enable_adjoint": (I32, [VP]),
     "fdu_set_variants": (I32, [VP, I32, I32]),
@@ -315,6 +316,12 @@ class Solver:
         _call("fdu_kernel_times", self.handle, self._state(w), C.c_void_p(scratch.data_ptr()), int(reps), out,
               _stream())
         return dict(ghost=out[0], edge=out[1], vertex=out[2], cfl=out[3])
+
+    def vertex_block_info(self):
+        """Vertex blocks of the LDS-staged variants: count, total and largest row list."""
+        n, rows, mx = C.c_int(), C.c_int64(), C.c_int()
+        _call("fdu_vertex_block_info", self.handle, C.byref(n), C.byref(rows), C.byref(mx))
+        return dict(n_blocks=n.value, halo_rows=rows.value, rows_max=mx.value)
 
     def kernel_timer_start(self, capacity: int = 4096):
         """Bracket every later kernel launch of this solver with HIP events

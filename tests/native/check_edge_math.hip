@@ -196,7 +196,8 @@ int main(int argc, char** argv) {
     double ob[4];
     for (int k = 0; k < 4; ++k) ob[k] = U(rng) - 0.5;
     double Wb[6][4];
-    edge_vjp_one(W, g, ob, S, Wb);
+    edge_vjp_one([&](int k, double q[4], bool) { for (int i = 0; i < 4; ++i) q[i] = W[k][i]; }, g, ob, S,
+                 [&](int k, const double q[4]) { for (int i = 0; i < 4; ++i) Wb[k][i] = q[i]; });
     double scale = 0.0;
     for (int s = 0; s < 6; ++s)
       for (int k = 0; k < 4; ++k) scale = std::fmax(scale, std::fabs(Wb[s][k]));

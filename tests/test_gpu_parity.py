@@ -238,7 +238,7 @@ def test_full_size_sod_sampled():
     assert err1.max() <= 1e-14
 
 
-@pytest.mark.parametrize("edge,vertex", [(e, v) for e in range(2) for v in range(10)])
+@pytest.mark.parametrize("edge,vertex", [(e, v) for e in range(2) for v in range(12)])
 def test_kernel_variants(vortex33_p5, sod24_p5, edge, vertex):
     """Every kernel variant computes the same residual (to the parity bar)."""
     for c in (vortex33_p5, sod24_p5):
@@ -289,3 +289,13 @@ def test_live_kernel_timer(sod24_p5):
     c.s.rk_step(w_b, scr_b, dt_b, cfl=0.2)          # timer off again: nothing recorded, no error
     with pytest.raises(fdu.FduError, match="INVALID_ARG"):
         c.s.kernel_timer_stop()
+
+
+@pytest.mark.parametrize("vertex", [0, 3, 10, 11])
+def test_hilbert_order_variants(vertex):
+    """Hilbert vertex order (compact vertex blocks for the LDS-staged variants):
+    residual and one RK stage against the oracle, walled and periodic meshes."""
+    for c in (Case(33, True, 0, 5, "vortex", reorder=2), Case(20, False, 4, 5, "sod", reorder=2)):
+        c.s.set_variants(1, vertex)
+        err = _residual_err(c)
+        assert err.max() <= TOL, err.max()
