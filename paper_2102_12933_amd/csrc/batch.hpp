@@ -28,6 +28,13 @@ struct BatchInst {
   const double* hmin;
   const int* gsrc;
   const signed char* grefl;
+  const int* vblk;   // vertex blocks of the LDS-staged vertex step
+  const int* vb_uvp;
+  const int* vb_uv;
+  const int* vb_uep;
+  const int* vb_ue;
+  const unsigned short* vb_lvcol;
+  const unsigned short* vb_lecol;
   double* flux;
   double* w;    // state (in/out)
   double* w1;   // stage buffers
@@ -149,6 +156,24 @@ __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict
       }
     }
   }
+}
+
+// Vertex phase over all instances with the stencil halos staged in LDS: one
+// workgroup per vertex block; tile t of the phase maps to (instance, block).
+template <int LPV, int MV, int ME, int WPE>
+__global__ void __launch_bounds__(256, WPE) k_batch_vertex_lds(const BatchInst* __restrict__ inst, int n,
+                                                               const int* __restrict__ tb, Scheme S, int k, double a,
+                                                               double b, const double* __restrict__ dt) {
+  extern __shared__ double lds[];
+  const int t = tb[2 * n] + blockIdx.x;
+  if (t >= tb[3 * n]) return;
+  const int j = find_slot(tb + 2 * n, n, t);
+  const BatchInst& I = inst[j];
+  const double* wprev = k == 0 ? I.w : (k == 1 ? I.w1 : I.w2);
+  double* wout = k == 0 ? I.w1 : (k == 1 ? I.w2 : I.w);
+  vertex_lds_block<double, double, LPV, MV, ME, 1>(t - tb[2 * n + j], lds, wprev, I.vblk, I.vb_uvp, I.vb_uv,
+                                                   I.vb_uep, I.vb_ue, I.vptr, I.vb_lvcol, I.wfg, I.eptr, I.vb_lecol,
+                                                   I.we, I.cO, I.flux, S.gm1, 1, nullptr, I.w, wout, a, b, dt + j);
 }
 
 // Per-instance CFL: block minima of hmin_v / (|u_v| + c_v) over 256-vertex

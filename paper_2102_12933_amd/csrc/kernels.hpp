@@ -60,6 +60,15 @@ __device__ __forceinline__ double frcp(double x) {
   return r;
 }
 
+// 1/x: IEEE division, or (FR, device code) the refined hardware reciprocal.
+template <bool FR>
+FDU_HD double recip(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (FR) return frcp(x);
+#endif
+  return 1.0 / x;
+}
+
 // Opaque copy of a value: the compiler cannot merge a computation on it with
 // an earlier identical one, so recomputing (cheap) replaces keeping the
 // earlier result live across the whole reverse sweep (registers).
@@ -205,6 +214,8 @@ template <int N>
 FDU_HD Dual<N> fabs(const Dual<N>& a) { return a.v < 0.0 ? -a : a; }
 FDU_HD double val(double x) { return x; }
 template <int N> FDU_HD double val(const Dual<N>& x) { return x.v; }
+template <bool FR, int N>
+FDU_HD Dual<N> recip(const Dual<N>& x) { return 1.0 / x; }
 
 // ----------------------------------------------------------------------------
 // Eigenvectors of A_n = n_x df/dw + n_y dg/dw at a Roe-averaged state:
@@ -217,16 +228,16 @@ struct FrameT {
 };
 using Frame = FrameT<double>;
 
-template <class T>
+template <class T, bool FR = false>
 FDU_HD FrameT<T> roe_frame(const T a[4], const T b[4], double nx, double ny, double gm1) {
   FrameT<T> F;
   const T ra = sqrt(a[0]), rb = sqrt(b[0]);
-  const T ia = 1.0 / a[0], ib = 1.0 / b[0];
+  const T ia = recip<FR>(a[0]), ib = recip<FR>(b[0]);
   const T ua = a[1] * ia, va = a[2] * ia, ub = b[1] * ib, vb = b[2] * ib;
   const T pa = gm1 * (a[3] - 0.5 * (a[1] * ua + a[2] * va));
   const T pb = gm1 * (b[3] - 0.5 * (b[1] * ub + b[2] * vb));
   const T Ha = (a[3] + pa) * ia, Hb = (b[3] + pb) * ib;
-  const T is = 1.0 / (ra + rb);
+  const T is = recip<FR>(ra + rb);
   F.u = (ra * ua + rb * ub) * is;
   F.v = (ra * va + rb * vb) * is;
   F.H = (ra * Ha + rb * Hb) * is;
@@ -240,9 +251,9 @@ FDU_HD FrameT<T> roe_frame(const T a[4], const T b[4], double nx, double ny, dou
 }
 
 // characteristic variables l_k . q
-template <class T>
+template <class T, bool FR = false>
 FDU_HD void to_char(const FrameT<T>& F, double gm1, const T q[4], T o[4]) {
-  const T ic = 1.0 / F.c;
+  const T ic = recip<FR>(F.c);
   const T b1 = gm1 * ic * ic, b2 = b1 * F.q2;
   const T mv = F.u * q[1] + F.v * q[2];                 // u . m
   const T nm = F.nx * q[1] + F.ny * q[2];               // n . m
@@ -264,24 +275,27 @@ FDU_HD void from_char(const FrameT<T>& F, const T a[4], T q[4]) {
   q[3] = F.H * s + F.c * F.un * d + F.q2 * a[1] + F.ut * a[2];
 }
 
-// rho > 0 and p > 0 (false for NaN as well)
+// rho > 0 and p > 0 (false for NaN as well); FR: the division-free test
+// rho E - |m|^2 / 2 > 0, equivalent for rho > 0 (rounding aside)
+template <bool FR = false>
 FDU_HD bool physical(const double q[4], double gm1) {
   if (!(q[0] > 0.0)) return false;
+  if (FR) return gm1 * (q[0] * q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2])) > 0.0;
   const double ir = 1.0 / q[0];
   const double u = q[1] * ir, v = q[2] * ir;
   const double p = gm1 * (q[3] - 0.5 * q[0] * (u * u + v * v));
   return p > 0.0;
 }
 
-template <class T>
+template <class T, bool FR = false>
 FDU_HD T harten(const T& l, const T& delta) {
   const T a = fabs(l);
-  return val(a) < val(delta) ? (l * l + delta * delta) / (2.0 * delta) : a;
+  return val(a) < val(delta) ? (l * l + delta * delta) * recip<FR>(2.0 * delta) : a;
 }
 
-template <class T>
+template <class T, bool FR = false>
 FDU_HD void normal_flux(const T q[4], double nx, double ny, double gm1, T F[4], T& un, T& c2) {
-  const T ir = 1.0 / q[0];
+  const T ir = recip<FR>(q[0]);
   const T u = q[1] * ir, v = q[2] * ir;
   const T p = gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * v));
   un = u * nx + v * ny;
@@ -293,12 +307,12 @@ FDU_HD void normal_flux(const T q[4], double nx, double ny, double gm1, T F[4], 
 }
 
 // Numerical flux along the edge direction n from the midpoint states wl, wr.
-template <class T>
+template <class T, bool FR = false>
 FDU_HD void riemann_flux(const T wl[4], const T wr[4], double nx, double ny, const Scheme& S,
                                              T out[4]) {
   T Fl[4], Fr[4], unl, unr, c2l, c2r;
-  normal_flux(wl, nx, ny, S.gm1, Fl, unl, c2l);
-  normal_flux(wr, nx, ny, S.gm1, Fr, unr, c2r);
+  normal_flux<T, FR>(wl, nx, ny, S.gm1, Fl, unl, c2l);
+  normal_flux<T, FR>(wr, nx, ny, S.gm1, Fr, unr, c2r);
   if (S.riemann == 1) {
     const T sl = fabs(unl) + sqrt(c2l), sr = fabs(unr) + sqrt(c2r);
     const T sm = val(sl) >= val(sr) ? sl : sr;
@@ -306,16 +320,16 @@ FDU_HD void riemann_flux(const T wl[4], const T wr[4], double nx, double ny, con
     for (int k = 0; k < 4; ++k) out[k] = 0.5 * (Fl[k] + Fr[k]) - 0.5 * sm * (wr[k] - wl[k]);
     return;
   }
-  const FrameT<T> F = roe_frame(wl, wr, nx, ny, S.gm1);
+  const FrameT<T> F = roe_frame<T, FR>(wl, wr, nx, ny, S.gm1);
   T dq[4], a[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) dq[k] = wr[k] - wl[k];
-  to_char(F, S.gm1, dq, a);
+  to_char<T, FR>(F, S.gm1, dq, a);
   const T delta = S.efrac * F.c;
-  a[0] = a[0] * harten(F.un - F.c, delta);
-  a[1] = a[1] * harten(F.un, delta);
-  a[2] = a[2] * harten(F.un, delta);
-  a[3] = a[3] * harten(F.un + F.c, delta);
+  a[0] = a[0] * harten<T, FR>(F.un - F.c, delta);
+  a[1] = a[1] * harten<T, FR>(F.un, delta);
+  a[2] = a[2] * harten<T, FR>(F.un, delta);
+  a[3] = a[3] * harten<T, FR>(F.un + F.c, delta);
   T d[4];
   from_char(F, a, d);
 #pragma unroll
@@ -567,7 +581,7 @@ __device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const in
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = (double)geo[6 * (size_t)e + k];
   const double nx = g[4], ny = g[5];
-  const Frame F = roe_frame<double>(W2, W3, nx, ny, S.gm1);
+  const Frame F = roe_frame<double, true>(W2, W3, nx, ny, S.gm1);
   double Cv[6][4];
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -575,7 +589,7 @@ __device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const in
     if (k == 2) { for (int i = 0; i < 4; ++i) q[i] = W2[i]; }
     else if (k == 3) { for (int i = 0; i < 4; ++i) q[i] = W3[i]; }
     else load4(w, id[k], q);
-    to_char(F, S.gm1, q, Cv[k]);
+    to_char<double, true>(F, S.gm1, q, Cv[k]);
   }
   double cl[4], cr[4];
   {
@@ -600,15 +614,15 @@ __device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const in
   from_char(F, cl, wl);
   from_char(F, cr, wr);
   if (S.positivity) {
-    if (!physical(wl, S.gm1))
+    if (!physical<true>(wl, S.gm1))
 #pragma unroll
       for (int k = 0; k < 4; ++k) wl[k] = W2[k];
-    if (!physical(wr, S.gm1))
+    if (!physical<true>(wr, S.gm1))
 #pragma unroll
       for (int k = 0; k < 4; ++k) wr[k] = W3[k];
   }
   double out[4];
-  riemann_flux<double>(wl, wr, nx, ny, S, out);
+  riemann_flux<double, true>(wl, wr, nx, ny, S, out);
   double2* rp = reinterpret_cast<double2*>(r + 4 * (size_t)e);
   rp[0] = make_double2(out[0], out[1]);
   rp[1] = make_double2(out[2], out[3]);
@@ -1004,20 +1018,20 @@ __device__ __forceinline__ void vertex_lds_compute(const VertexFetch<TW, MV, ME>
   }
 }
 
-template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE>
-__global__ void __launch_bounds__(256, WPE) k_vertex_lds(const T* __restrict__ w, const int* __restrict__ blk,
-                                                    const int* __restrict__ uvp, const int* __restrict__ uv,
-                                                    const int* __restrict__ uep, const int* __restrict__ ue,
-                                                    const int* __restrict__ vptr, const unsigned short* __restrict__ lvcol,
-                                                    const TW* __restrict__ wfg, const int* __restrict__ eptr,
-                                                    const unsigned short* __restrict__ lecol, const TW* __restrict__ we,
-                                                    const double* __restrict__ cO, const double* __restrict__ r,
-                                                    double gm1, int mode, T* __restrict__ R, const T* __restrict__ wn,
-                                                    T* __restrict__ out, double a, double b,
-                                                    const double* __restrict__ dt_dev) {
-  extern __shared__ double lds[];   // [rows][4]: the block's state rows, then its flux rows
+// One vertex block of the LDS-staged vertex step (the workgroup's 256 threads).
+template <class T, class TW, int LPV, int MV, int ME, int PF>
+__device__ __forceinline__ void vertex_lds_block(int bk, double* lds, const T* __restrict__ w,
+                                                 const int* __restrict__ blk, const int* __restrict__ uvp,
+                                                 const int* __restrict__ uv, const int* __restrict__ uep,
+                                                 const int* __restrict__ ue, const int* __restrict__ vptr,
+                                                 const unsigned short* __restrict__ lvcol,
+                                                 const TW* __restrict__ wfg, const int* __restrict__ eptr,
+                                                 const unsigned short* __restrict__ lecol,
+                                                 const TW* __restrict__ we, const double* __restrict__ cO,
+                                                 const double* __restrict__ r, double gm1, int mode,
+                                                 T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
+                                                 double a, double b, const double* __restrict__ dt_dev) {
   constexpr int VPR = 256 / LPV;    // vertices per round
-  const int bk = xcd_block(blockIdx.x, gridDim.x);
   const int v0 = blk[bk], v1 = blk[bk + 1];
   const int a0 = uvp[bk], na = uvp[bk + 1] - a0;
   const int e0 = uep[bk], ne = uep[bk + 1] - e0;
@@ -1053,6 +1067,24 @@ __global__ void __launch_bounds__(256, WPE) k_vertex_lds(const T* __restrict__ w
                                              out, a, b, dt_dev);
     }
   }
+}
+
+template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE>
+__global__ void __launch_bounds__(256, WPE) k_vertex_lds(const T* __restrict__ w, const int* __restrict__ blk,
+                                                         const int* __restrict__ uvp, const int* __restrict__ uv,
+                                                         const int* __restrict__ uep, const int* __restrict__ ue,
+                                                         const int* __restrict__ vptr,
+                                                         const unsigned short* __restrict__ lvcol,
+                                                         const TW* __restrict__ wfg, const int* __restrict__ eptr,
+                                                         const unsigned short* __restrict__ lecol,
+                                                         const TW* __restrict__ we, const double* __restrict__ cO,
+                                                         const double* __restrict__ r, double gm1, int mode,
+                                                         T* __restrict__ R, const T* __restrict__ wn,
+                                                         T* __restrict__ out, double a, double b,
+                                                         const double* __restrict__ dt_dev) {
+  extern __shared__ double lds[];   // [rows][4]: the block's state rows, then its flux rows
+  vertex_lds_block<T, TW, LPV, MV, ME, PF>(xcd_block(blockIdx.x, gridDim.x), lds, w, blk, uvp, uv, uep, ue, vptr,
+                                           lvcol, wfg, eptr, lecol, we, cO, r, gm1, mode, R, wn, out, a, b, dt_dev);
 }
 
 // CFL time step: per-block minima of hmin_v / (|u_v| + c_v), then one block

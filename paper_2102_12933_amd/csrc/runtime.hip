@@ -530,7 +530,8 @@ struct fdu_batch {
   Scheme S{};
   int schedule = 0;     // 0 fused persistent, 1 one launch per phase, 2 per-instance kernels
   BatchTiling tl{4, 8};
-  int vmode = 0;        // vertex tiles: 0 loop/16 lanes, 1 loop/8 lanes, 2 pipelined/8 lanes
+  int vmode = 0;        // vertex tiles: 0 loop/16 lanes, 1 loop/8 lanes, 2 pipelined/8 lanes, 3 LDS blocks
+  int lds_rows = 0;     // vertex mode 3: largest vertex-block row list over the instances
   int grid = 0;         // blocks of the fused launch
   int total = 0, ctiles = 0;
   std::vector<int32_t> h_tb;
@@ -562,11 +563,14 @@ void batch_tiles(fdu_batch* b) {
       b->h_tb[p * n + i] = acc;
       const int nt = p == 0 ? (int)((s->ng + 255) / 256)
                    : p == 1 ? (int)((s->ne_flux + 256 * b->tl.ept - 1) / (256 * b->tl.ept))
+                   : b->vmode == 3 ? s->n_vblocks
                             : (int)((s->nv_real + per_v - 1) / per_v);
       acc += nt;
     }
   b->h_tb[3 * n] = acc;
   b->total = acc;
+  b->lds_rows = 0;
+  for (int i = 0; i < n; ++i) b->lds_rows = std::max(b->lds_rows, b->inst[i]->vb_rows_max);
   b->tb.upload(b->h_tb.data(), b->h_tb.size());
   std::vector<int32_t> tbc(n + 1, 0);
   for (int i = 0; i < n; ++i) tbc[i + 1] = tbc[i] + (int)((b->inst[i]->nv_real + 255) / 256);
@@ -596,17 +600,26 @@ void batch_stage_vm(fdu_batch* b, int k, hipStream_t st) {
   const int t0 = b->h_tb[n] - b->h_tb[0], t1 = b->h_tb[2 * n] - b->h_tb[n], t2 = b->h_tb[3 * n] - b->h_tb[2 * n];
   if (t0 > 0) batch_stage_launch<EV, VM, 0>(b, k, st, (unsigned)t0);
   if (t1 > 0) batch_stage_launch<EV, VM, 1>(b, k, st, (unsigned)t1);
-  if (t2 > 0) batch_stage_launch<EV, VM, 2>(b, k, st, (unsigned)t2);
+  if (t2 > 0) {
+    if (VM == 3)
+      hipLaunchKernelGGL((k_batch_vertex_lds<8, 3, 6, 5>), dim3(t2), dim3(256),
+                         (size_t)b->lds_rows * 4 * sizeof(double), st, b->dinst.p, n, b->tb.p, b->S, k, kRK[k][0],
+                         kRK[k][1], b->dt.p);
+    else
+      batch_stage_launch<EV, VM, 2>(b, k, st, (unsigned)t2);
+  }
 }
 
 void batch_stage(fdu_batch* b, int k, hipStream_t st) {
   const int ev = b->inst[0]->edge_variant == 1 ? 1 : 0;
   if (ev == 1) {
-    if (b->vmode == 2) batch_stage_vm<1, 2>(b, k, st);
+    if (b->vmode == 3) batch_stage_vm<1, 3>(b, k, st);
+    else if (b->vmode == 2) batch_stage_vm<1, 2>(b, k, st);
     else if (b->vmode == 1) batch_stage_vm<1, 1>(b, k, st);
     else batch_stage_vm<1, 0>(b, k, st);
   } else {
-    if (b->vmode == 2) batch_stage_vm<0, 2>(b, k, st);
+    if (b->vmode == 3) batch_stage_vm<0, 3>(b, k, st);
+    else if (b->vmode == 2) batch_stage_vm<0, 2>(b, k, st);
     else if (b->vmode == 1) batch_stage_vm<0, 1>(b, k, st);
     else batch_stage_vm<0, 0>(b, k, st);
   }
@@ -1047,6 +1060,8 @@ fdu_status fdu_batch_set_states(fdu_batch* b, void* const* w, void* const* scrat
       I.sten = s->sten.p; I.geo = s->geo.p; I.vptr = s->vptr.p; I.vcol = s->vcol.p; I.wfg = s->wfg.p;
       I.eptr = s->eptr.p; I.ecol = s->ecol.p; I.we = s->we.p; I.cO = s->cO.p; I.hmin = s->hmin.p;
       I.gsrc = s->gsrc.p; I.grefl = reinterpret_cast<const signed char*>(s->grefl.p); I.flux = s->flux.p;
+      I.vblk = s->vblk.p; I.vb_uvp = s->vb_uvp.p; I.vb_uv = s->vb_uv.p; I.vb_uep = s->vb_uep.p; I.vb_ue = s->vb_ue.p;
+      I.vb_lvcol = s->vb_lvcol.p; I.vb_lecol = s->vb_lecol.p;
       I.w = (double*)w[i];
       I.w1 = (double*)scratch[i];
       I.w2 = (double*)scratch[i] + 4 * s->nv_total;
@@ -1066,7 +1081,9 @@ fdu_status fdu_batch_set_schedule(fdu_batch* b, int schedule, int edges_per_thre
     need(schedule >= 0 && schedule <= 2, "schedule must be 0, 1 or 2");
     need(edges_per_thread >= 1 && edges_per_thread <= 64, "edges_per_thread out of range");
     need(vertex_passes >= 1 && vertex_passes <= 64, "vertex_passes out of range");
-    need(vertex_mode >= 0 && vertex_mode <= 2, "vertex_mode must be 0, 1 or 2");
+    need(vertex_mode >= 0 && vertex_mode <= 3, "vertex_mode must be 0, 1, 2 or 3");
+    if (vertex_mode == 3 && schedule == 0)
+      throw Error(FDU_ERR_UNSUPPORTED, "vertex mode 3 (LDS blocks) needs schedule 1 or 2");
     DeviceGuard dg(b->device);
     b->schedule = schedule;
     b->tl.ept = edges_per_thread;

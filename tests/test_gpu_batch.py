@@ -49,11 +49,12 @@ def plain_steps(inst, nsteps, cfl):
 
 @pytest.mark.parametrize("edge_variant", [0, 1])
 @pytest.mark.parametrize("schedule,ept,vp,vmode", [(0, 4, 8, 0), (0, 1, 1, 1), (0, 4, 8, 2), (1, 4, 8, 0),
-                                                   (1, 16, 16, 2), (2, 4, 8, 0), (0, 16, 32, 0)])
+                                                   (1, 16, 16, 2), (2, 4, 8, 0), (0, 16, 32, 0), (1, 4, 8, 3),
+                                                   (1, 1, 1, 3), (2, 4, 8, 3)])
 def test_batch_equals_plain(edge_variant, schedule, ept, vp, vmode):
     fdu = _fdu()
     # the plain path's vertex kernel with the same lanes and load order sums in the same order
-    inst = build_instances(SPECS, edge_variant, vertex_variant={0: 0, 1: 4, 2: 3}[vmode])
+    inst = build_instances(SPECS, edge_variant, vertex_variant={0: 0, 1: 4, 2: 3, 3: 10}[vmode])
     ref = plain_steps(inst, 3, 0.5)
     b = fdu.Batch([s for s, _ in inst])
     b.set_schedule(schedule, ept, vp, vmode)
@@ -107,3 +108,11 @@ def test_batch_table_matches_workload_description():
     specs = batch_specs()
     assert len(specs) == 64
     assert all(65 <= sp["N"] <= 513 and 2.0 <= sp["beta"] <= 6.0 and 0.3 <= sp["mach"] <= 0.8 for sp in specs)
+
+
+def test_batch_lds_mode_rejects_persistent_schedule():
+    fdu = _fdu()
+    inst = build_instances(SPECS[:2])
+    b = fdu.Batch([s for s, _ in inst])
+    with pytest.raises(fdu.FduError, match="UNSUPPORTED"):
+        b.set_schedule(0, 4, 8, 3)
