@@ -62,7 +62,11 @@ typedef enum { FDU_F64 = 0, FDU_F32 = 1 } fdu_precision;
  * WENO eps 1e-40 and power 1 (Appendix), Roe flux with Harten's entropy fix
  * delta = 0.1 * c_roe, positivity fallback on.
  * positivity (not in the paper): when an interpolated midpoint state has
- * rho <= 0 or p <= 0, that side of the edge uses its end vertex state. */
+ * rho <= 0 or p <= 0, that side of the edge uses its end vertex state.
+ * interpolation and uniform_weno (default 0 and 0, the paper's scheme) are
+ * ablation switches: interpolate the conservative variables directly (no
+ * characteristic projection), and/or use the uniform WENO5 coefficients
+ * whatever the node spacing along the stencil. */
 typedef struct {
   double gamma;
   double weno_eps;
@@ -70,6 +74,9 @@ typedef struct {
   int weno_power; /* 1 or 2 */
   int riemann;    /* 0 = Roe + Harten fix, 1 = Rusanov */
   int positivity; /* 0 or 1 */
+  int interpolation; /* 0 = characteristic variables (Sec. 2.3.1), 1 = conservative variables */
+  int uniform_weno;  /* 0 = NU-WENO5 on the arc coordinates (Appendix), 1 = standard WENO5 on
+                        equally spaced nodes (the comparison of Sec. 2.3.2) */
 } fdu_params;
 
 const char* fdu_last_error(void);

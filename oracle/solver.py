@@ -17,6 +17,10 @@ Addition (not in the paper; ``positivity=False`` turns it off): where an
 interpolated midpoint state has rho <= 0 or p <= 0 (the WENO quadratics can
 overshoot on stencils that cross a discontinuity twice), that side of the edge
 falls back to its end vertex state (w_L = w_L1, w_R = w_R1).
+Ablation switches (the comparisons of Sec. 2.3.1-2.3.2, defaults = the paper's
+scheme): ``interpolation="conservative"`` interpolates the conservative
+variables directly instead of the characteristic ones; ``weno="uniform"`` uses
+standard WENO5 (equally spaced nodes) whatever the spacing along the stencil.
 Readings: dt = CFL * min_v h_v / (|u_v| + c_v) over real vertices, h_v the
 shortest edge at v (the paper names the CFL number but no formula).  Walls (not
 in the paper, which has periodic and Dirichlet boundaries only): ghost states
@@ -31,13 +35,17 @@ import torch
 from . import euler
 from .geometry import arc_coordinates, min_image, neighbour_table, select_1d_stencils
 from .lsq import Topology, ls_weights
-from .nuweno import NUWeno5, WENO_EPS, WENO_POWER
+from .nuweno import NUWeno5, WENO_EPS, WENO_POWER, uniform_weno5
 
 
 class Oracle:
     def __init__(self, mesh, deg: int = 5, level=None, vertices=None, gamma: float = euler.GAMMA,
                  weno_eps: float = WENO_EPS, weno_power: int = WENO_POWER,
-                 entropy_frac: float = 0.1, riemann: str = "roe", positivity: bool = True):
+                 entropy_frac: float = 0.1, riemann: str = "roe", positivity: bool = True,
+                 interpolation: str = "characteristic", weno: str = "nonuniform"):
+        if interpolation not in ("characteristic", "conservative") or weno not in ("nonuniform", "uniform"):
+            raise ValueError("interpolation: characteristic|conservative, weno: nonuniform|uniform")
+        self.interpolation = interpolation
         self.mesh = mesh
         self.positivity = positivity
         self.gamma = gamma
@@ -54,8 +62,12 @@ class Oracle:
         nbtab, _ = neighbour_table(mesh)
         self.sten6 = select_1d_stencils(mesh, self.edges, nbtab)
         self.s, self.dir = arc_coordinates(mesh, self.sten6)
-        self.wenoL = NUWeno5(self.s[:, 0:5], weno_eps, weno_power)
-        self.wenoR = NUWeno5(-self.s[:, [5, 4, 3, 2, 1]], weno_eps, weno_power)
+        if weno == "uniform":        # standard WENO5 whatever the node spacing (Sec. 2.3.2 comparison)
+            self.wenoL = uniform_weno5(len(self.edges), weno_eps, weno_power)
+            self.wenoR = uniform_weno5(len(self.edges), weno_eps, weno_power)
+        else:
+            self.wenoL = NUWeno5(self.s[:, 0:5], weno_eps, weno_power)
+            self.wenoR = NUWeno5(-self.s[:, [5, 4, 3, 2, 1]], weno_eps, weno_power)
         W = self.W
         nsel = len(self.vertices)
         self.v_row = torch.from_numpy(np.repeat(np.arange(nsel), np.diff(W["vptr"])))
@@ -86,12 +98,16 @@ class Oracle:
     def edge_states(self, w: torch.Tensor):
         """Interpolated (w_L, w_R) at the midpoints of the needed edges."""
         W6 = w[self.sten_t]                                         # [ne,6,4]
-        R, L = euler.char_basis(W6[:, 2], W6[:, 3], self.n_e, self.gamma)
-        C6 = torch.einsum("eij,esj->esi", L, W6)                     # characteristic values
-        cL = self.wenoL(C6[:, 0:5])
-        cR = self.wenoR(C6[:, [5, 4, 3, 2, 1]])
-        wL = torch.einsum("eij,ej->ei", R, cL)
-        wR = torch.einsum("eij,ej->ei", R, cR)
+        if self.interpolation == "conservative":                     # ablation: no projection
+            wL = self.wenoL(W6[:, 0:5])
+            wR = self.wenoR(W6[:, [5, 4, 3, 2, 1]])
+        else:
+            R, L = euler.char_basis(W6[:, 2], W6[:, 3], self.n_e, self.gamma)
+            C6 = torch.einsum("eij,esj->esi", L, W6)                 # characteristic values
+            cL = self.wenoL(C6[:, 0:5])
+            cR = self.wenoR(C6[:, [5, 4, 3, 2, 1]])
+            wL = torch.einsum("eij,ej->ei", R, cL)
+            wR = torch.einsum("eij,ej->ei", R, cR)
         if self.positivity:
             wL = torch.where(self._physical(wL)[:, None], wL, W6[:, 2])
             wR = torch.where(self._physical(wR)[:, None], wR, W6[:, 3])

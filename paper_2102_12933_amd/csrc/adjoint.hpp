@@ -270,6 +270,9 @@ FDU_HD void riemann_flux_T(const double wl[4], const double wr[4], double nx, do
 template <class Load, class Store>
 FDU_HD void edge_vjp_one(Load&& load, const double g[6], const double ob[4], const Scheme& S, Store&& store) {
   const double nx = g[4], ny = g[5];
+  const bool cons = S.conservative != 0;
+  double x[4];
+  weno_nodes(g, S, x);
   // ---- forward recomputation
   double W2[4], W3[4];
   load(2, W2, false);
@@ -285,12 +288,17 @@ FDU_HD void edge_vjp_one(Load&& load, const double g[6], const double ob[4], con
     } else {
       load(k, q, false);
     }
-    to_char(F, S.gm1, q, Cv[k]);
+    if (cons) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Cv[k][i] = q[i];
+    } else {
+      to_char(F, S.gm1, q, Cv[k]);
+    }
   }
   double cl[4], cr[4];
   {
     WenoGeom G;
-    weno_geom(g[0], g[1], g[2], G);
+    weno_geom(x[0], x[1], x[2], G);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double u[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
@@ -299,7 +307,7 @@ FDU_HD void edge_vjp_one(Load&& load, const double g[6], const double ob[4], con
   }
   {
     WenoGeom G;
-    weno_geom(-g[3], -g[2], -g[1], G);
+    weno_geom(-x[3], -x[2], -x[1], G);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double u[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
@@ -307,8 +315,16 @@ FDU_HD void edge_vjp_one(Load&& load, const double g[6], const double ob[4], con
     }
   }
   double wl[4], wr[4];
-  from_char(F, cl, wl);
-  from_char(F, cr, wr);
+  if (cons) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      wl[k] = cl[k];
+      wr[k] = cr[k];
+    }
+  } else {
+    from_char(F, cl, wl);
+    from_char(F, cr, wr);
+  }
   bool fl = false, fr = false;
   if (S.positivity) {
     fl = !physical(wl, S.gm1);
@@ -331,6 +347,9 @@ FDU_HD void edge_vjp_one(Load&& load, const double g[6], const double ob[4], con
   if (fl) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) e2[k] = wlb[k];
+  } else if (cons) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) clb[k] = wlb[k];
   } else {
     from_char_T(F, wlb, clb);
     from_char_frame_T(F, cl, wlb, Fb);
@@ -338,6 +357,9 @@ FDU_HD void edge_vjp_one(Load&& load, const double g[6], const double ob[4], con
   if (fr) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) e3[k] = wrb[k];
+  } else if (cons) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) crb[k] = wrb[k];
   } else {
     from_char_T(F, wrb, crb);
     from_char_frame_T(F, cr, wrb, Fb);
@@ -350,7 +372,7 @@ FDU_HD void edge_vjp_one(Load&& load, const double g[6], const double ob[4], con
     for (int k = 0; k < 4; ++k) Cb[s][k] = 0.0;
   {
     WenoGeom G;
-    weno_geom(opaque(g[0]), opaque(g[1]), opaque(g[2]), G);
+    weno_geom(opaque(x[0]), opaque(x[1]), opaque(x[2]), G);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double u[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
@@ -362,7 +384,7 @@ FDU_HD void edge_vjp_one(Load&& load, const double g[6], const double ob[4], con
   }
   {
     WenoGeom G;
-    weno_geom(-opaque(g[3]), -opaque(g[2]), -opaque(g[1]), G);
+    weno_geom(-opaque(x[3]), -opaque(x[2]), -opaque(x[1]), G);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double u[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
@@ -371,6 +393,17 @@ FDU_HD void edge_vjp_one(Load&& load, const double g[6], const double ob[4], con
 #pragma unroll
       for (int m = 0; m < 5; ++m) Cb[5 - m][c] += ub[m];
     }
+  }
+  if (cons) {
+    // interpolated variables are the states themselves
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      double wb[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wb[k] = Cb[s][k] + (s == 2 ? e2[k] : 0.0) + (s == 3 ? e3[k] : 0.0);
+      store(s, wb);
+    }
+    return;
   }
   // ---- characteristic projection: frame cotangents first (they need the
   // states, loaded again), then the states at the fixed frame

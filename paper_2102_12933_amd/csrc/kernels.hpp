@@ -19,7 +19,19 @@ struct Scheme {
   int power;      // WENO power (1 or 2)
   int riemann;    // 0 Roe + Harten, 1 Rusanov
   int positivity; // 1: a non-physical interpolated state falls back to its end vertex state
+  int conservative;  // 1: interpolate conservative instead of characteristic variables
+  int uniform;       // 1: standard WENO5 (equally spaced nodes) instead of NU-WENO5
 };
+
+// Outer stencil nodes (L3, L2, R2, R3) in units of the middle-edge length:
+// the arc coordinates, or the equally spaced nodes of standard WENO5.
+FDU_HD void weno_nodes(const double g[6], const Scheme& S, double x[4]) {
+  if (S.uniform) {
+    x[0] = -2.5; x[1] = -1.5; x[2] = 1.5; x[3] = 2.5;
+  } else {
+    x[0] = g[0]; x[1] = g[1]; x[2] = g[2]; x[3] = g[3];
+  }
+}
 
 // ----------------------------------------------------------------------------
 // State access: array of structures [n][4]; one 32-byte (double) or 16-byte
@@ -344,12 +356,21 @@ FDU_HD void edge_flux_one(const double W[6][4], const double g[6], const Scheme&
   const Frame F = roe_frame<double>(W[2], W[3], nx, ny, S.gm1);
   double Cv[6][4];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) to_char(F, S.gm1, W[k], Cv[k]);
+  for (int k = 0; k < 6; ++k) {
+    if (S.conservative) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Cv[k][i] = W[k][i];
+    } else {
+      to_char(F, S.gm1, W[k], Cv[k]);
+    }
+  }
 
   // left state from (L3 L2 L1 R1 R2); right state from the mirror (R3 R2 R1 L1 L2)
+  double x[4];
+  weno_nodes(g, S, x);
   WenoGeom GL, GR;
-  weno_geom(g[0], g[1], g[2], GL);
-  weno_geom(-g[3], -g[2], -g[1], GR);
+  weno_geom(x[0], x[1], x[2], GL);
+  weno_geom(-x[3], -x[2], -x[1], GR);
   double cl[4], cr[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -359,8 +380,16 @@ FDU_HD void edge_flux_one(const double W[6][4], const double g[6], const Scheme&
     cr[c] = weno_eval(GR, ur, S.eps, S.power);
   }
   double wl[4], wr[4];
-  from_char(F, cl, wl);
-  from_char(F, cr, wr);
+  if (S.conservative) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      wl[k] = cl[k];
+      wr[k] = cr[k];
+    }
+  } else {
+    from_char(F, cl, wl);
+    from_char(F, cr, wr);
+  }
   if (S.positivity) {
     if (!physical(wl, S.gm1))
 #pragma unroll
@@ -589,12 +618,19 @@ __device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const in
     if (k == 2) { for (int i = 0; i < 4; ++i) q[i] = W2[i]; }
     else if (k == 3) { for (int i = 0; i < 4; ++i) q[i] = W3[i]; }
     else load4(w, id[k], q);
-    to_char<double, true>(F, S.gm1, q, Cv[k]);
+    if (S.conservative) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Cv[k][i] = q[i];
+    } else {
+      to_char<double, true>(F, S.gm1, q, Cv[k]);
+    }
   }
+  double x[4];
+  weno_nodes(g, S, x);
   double cl[4], cr[4];
   {
     WenoDD G;
-    weno_dd_geom(g[0], g[1], g[2], G);
+    weno_dd_geom(x[0], x[1], x[2], G);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double u[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
@@ -603,7 +639,7 @@ __device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const in
   }
   {
     WenoDD G;
-    weno_dd_geom(-g[3], -g[2], -g[1], G);
+    weno_dd_geom(-x[3], -x[2], -x[1], G);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double u[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
@@ -611,8 +647,16 @@ __device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const in
     }
   }
   double wl[4], wr[4];
-  from_char(F, cl, wl);
-  from_char(F, cr, wr);
+  if (S.conservative) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      wl[k] = cl[k];
+      wr[k] = cr[k];
+    }
+  } else {
+    from_char(F, cl, wl);
+    from_char(F, cr, wr);
+  }
   if (S.positivity) {
     if (!physical<true>(wl, S.gm1))
 #pragma unroll

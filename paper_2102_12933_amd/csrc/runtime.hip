@@ -133,6 +133,8 @@ Scheme scheme_of(const fdu_solver* s) {
   S.power = s->params.weno_power;
   S.riemann = s->params.riemann;
   S.positivity = s->params.positivity;
+  S.conservative = s->params.interpolation;
+  S.uniform = s->params.uniform_weno;
   return S;
 }
 
@@ -665,6 +667,8 @@ void fdu_default_params(fdu_params* p) {
   p->weno_power = 1;
   p->riemann = 0;
   p->positivity = 1;
+  p->interpolation = 0;
+  p->uniform_weno = 0;
 }
 
 fdu_status fdu_create(fdu_solver** out, int hip_device, fdu_precision prec, const fdu_params* params) {
@@ -684,7 +688,9 @@ fdu_status fdu_create(fdu_solver** out, int hip_device, fdu_precision prec, cons
       fdu_default_params(&s->params);
     if (!(s->params.gamma > 1.0) || !(s->params.weno_eps > 0) || (s->params.weno_power != 1 && s->params.weno_power != 2) ||
         (s->params.riemann != 0 && s->params.riemann != 1) || !(s->params.entropy_frac >= 0) ||
-        (s->params.positivity != 0 && s->params.positivity != 1)) {
+        (s->params.positivity != 0 && s->params.positivity != 1) ||
+        (s->params.interpolation != 0 && s->params.interpolation != 1) ||
+        (s->params.uniform_weno != 0 && s->params.uniform_weno != 1)) {
       delete s;
       throw Error(FDU_ERR_INVALID_ARG, "invalid scheme parameters");
     }

@@ -28,7 +28,8 @@ class FduError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("weno_eps", C.c_double), ("entropy_frac", C.c_double),
-                ("weno_power", C.c_int), ("riemann", C.c_int), ("positivity", C.c_int)]
+                ("weno_power", C.c_int), ("riemann", C.c_int), ("positivity", C.c_int),
+                ("interpolation", C.c_int), ("uniform_weno", C.c_int)]
 
 
 class PrepView(C.Structure):

@@ -175,9 +175,12 @@ int main(int argc, char** argv) {
   const int power = argc > 3 ? std::atoi(argv[3]) : 1;
   const double eps = argc > 4 ? std::atof(argv[4]) : 1e-6;
   const int riemann = argc > 5 ? std::atoi(argv[5]) : 0;
+  const int conservative = argc > 6 ? std::atoi(argv[6]) : 0;
+  const int uniform = argc > 7 ? std::atoi(argv[7]) : 0;
   std::mt19937_64 rng(12345);
   std::uniform_real_distribution<double> U(0.0, 1.0);
-  Scheme S{1.4, 0.4, eps, 0.1, power, riemann, positivity};
+  Scheme S{1.4, 0.4, eps, 0.1, power, riemann, positivity, conservative, uniform};
+  const bool dual_ok = !conservative && !uniform;   // the dual-number route covers the paper's scheme
   double worst = 0.0, worst_dual = 0.0;
   for (int trial = 0; trial < 200; ++trial) {
     double W[6][4], g[6];
@@ -203,7 +206,7 @@ int main(int argc, char** argv) {
       for (int k = 0; k < 4; ++k) scale = std::fmax(scale, std::fabs(Wb[s][k]));
     double Wd[6][4];
     edge_vjp_dual(W, g, ob, S, Wd);
-    for (int s = 0; s < 6; ++s)
+    for (int s = 0; s < 6 && dual_ok; ++s)
       for (int k = 0; k < 4; ++k) {
         const double err = std::fabs(Wd[s][k] - Wb[s][k]) / scale;
         if (err > worst_dual) worst_dual = err;

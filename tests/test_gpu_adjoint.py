@@ -47,6 +47,12 @@ class AdjCase:
             okw["positivity"] = bool(params["positivity"])
         if "weno_power" in params:
             okw["weno_power"] = params["weno_power"]
+        if "riemann" in params:
+            okw["riemann"] = "roe" if params["riemann"] == 0 else "rusanov"
+        if params.get("interpolation"):
+            okw["interpolation"] = "conservative"
+        if params.get("uniform_weno"):
+            okw["weno"] = "uniform"
         self.o = Oracle(self.m, deg=deg, **okw)
         self.w0 = vortex_state(self.m, beta=5.0, mach=0.5) if state == "vortex" else perturbed_sod(self.m)
 
@@ -55,7 +61,9 @@ class AdjCase:
 
 
 CASES = [(20, True, 0, 5, "vortex", {}), (24, True, 0, 3, "vortex", {}), (16, False, 4, 5, "sod", {}),
-         (16, False, 4, 5, "sod", dict(positivity=0)), (18, True, 0, 5, "vortex", dict(weno_power=2))]
+         (16, False, 4, 5, "sod", dict(positivity=0)), (18, True, 0, 5, "vortex", dict(weno_power=2)),
+         (18, True, 0, 5, "vortex", dict(riemann=1)), (16, False, 4, 5, "sod", dict(interpolation=1)),
+         (18, True, 0, 5, "vortex", dict(uniform_weno=1))]
 
 
 @pytest.mark.parametrize("N,per,G,deg,state,params", CASES)

@@ -53,6 +53,10 @@ class Case:
             okw["riemann"] = "roe" if params["riemann"] == 0 else "rusanov"
         if "positivity" in params:
             okw["positivity"] = bool(params["positivity"])
+        if params.get("interpolation"):
+            okw["interpolation"] = "conservative"
+        if params.get("uniform_weno"):
+            okw["weno"] = "uniform"
         self.o = Oracle(self.m, deg=deg, **okw)
         self.w0 = vortex_state(self.m, beta=5.0, mach=0.5) if state == "vortex" else perturbed_sod(self.m)
 
@@ -158,12 +162,19 @@ def test_rk_stage_matches_oracle_stage(sod24_p5):
         assert err.max() <= 1e-14, (k, err)
 
 
-@pytest.mark.parametrize("params", [dict(weno_power=2), dict(riemann=1), dict(positivity=0)])
-def test_parameter_switches(params):
+@pytest.mark.parametrize("params", [dict(weno_power=2), dict(riemann=1), dict(positivity=0), dict(interpolation=1),
+                                    dict(uniform_weno=1), dict(interpolation=1, uniform_weno=1)])
+@pytest.mark.parametrize("edge", [0, 1])
+def test_parameter_switches(params, edge):
     c = Case(20, True, 0, 5, "vortex", **params)
+    c.s.set_variants(edge, 10)
     err = _residual_err(c)
-    print(params, err)
+    print(params, edge, err)
     assert err.max() <= TOL
+    c2 = Case(16, False, 4, 5, "sod", **params)
+    c2.s.set_variants(edge, 3)
+    err2 = _residual_err(c2)
+    assert err2.max() <= TOL
 
 
 def test_natural_order_and_smallest_meshes():

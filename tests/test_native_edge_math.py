@@ -24,10 +24,14 @@ def exe(tmp_path_factory):
     return out
 
 
-@pytest.mark.parametrize("positivity,power,riemann,tol", [(1, 1, 0, 1e-7), (0, 1, 0, 1e-7), (1, 2, 0, 1e-6),
-                                                          (1, 1, 1, 2e-5)])
-def test_edge_vjp_matches_finite_differences(exe, positivity, power, riemann, tol):
-    r = subprocess.run([exe, str(tol), str(positivity), str(power), "1e-6", str(riemann)], capture_output=True,
-                       text=True)
+@pytest.mark.parametrize("positivity,power,riemann,cons,uni,eps,tol", [
+    (1, 1, 0, 0, 0, "1e-6", 1e-7), (0, 1, 0, 0, 0, "1e-6", 1e-7), (1, 2, 0, 0, 0, "1e-6", 1e-6),
+    (1, 1, 1, 0, 0, "1e-6", 2e-5), (1, 1, 0, 0, 1, "1e-6", 1e-7),
+    # conservative components have smoothness indicators nearer eps: the weights are stiffer and the
+    # central differences' own truncation error grows (4e-7 at eps 1e-6, 2e-8 at 1e-4, 1e-9 at 1e-2)
+    (1, 1, 0, 1, 0, "1e-4", 1e-7)])
+def test_edge_vjp_matches_finite_differences(exe, positivity, power, riemann, cons, uni, eps, tol):
+    r = subprocess.run([exe, str(tol), str(positivity), str(power), eps, str(riemann), str(cons), str(uni)],
+                       capture_output=True, text=True)
     print(r.stdout)
     assert r.returncode == 0, r.stdout

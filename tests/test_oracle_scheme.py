@@ -233,3 +233,42 @@ def test_vortex_jittered_meshes_do_not_converge_pointwise():
     stays O(1) (the one-step density error, dt times it, is first order)."""
     e = [_vortex_trunc(N, 0.15, "random") for N in (32, 64)]
     assert 0.5 < e[0] / e[1] < 2.0, e
+
+
+def test_uniform_weno_switch_is_identity_on_regular_meshes():
+    """Regular diagonalized mesh: every 1D stencil is straight and equally spaced
+    (Sec. 2.2.2), so NU-WENO5 reduces to standard WENO5 and the uniform-WENO
+    switch changes nothing; on a jittered mesh it does."""
+    m = make_mesh(12, L=10.0, periodic=True, seed=2, jitter=0.0, diag="uniform")
+    w = torch.from_numpy(vortex_state(m, beta=5.0, mach=0.5))
+    a = Oracle(m, deg=3).edge_fluxes(w)
+    b = Oracle(m, deg=3, weno="uniform").edge_fluxes(w)
+    assert float((a - b).abs().max()) <= 1e-13 * float(a.abs().max())
+    mj = make_mesh(12, L=10.0, periodic=True, seed=2)
+    wj = torch.from_numpy(vortex_state(mj, beta=5.0, mach=0.5))
+    aj = Oracle(mj, deg=3).edge_fluxes(wj)
+    bj = Oracle(mj, deg=3, weno="uniform").edge_fluxes(wj)
+    assert float((aj - bj).abs().max()) > 1e-6 * float(aj.abs().max())
+
+
+@pytest.mark.parametrize("interpolation", ["characteristic", "conservative"])
+def test_linear_fields_interpolated_exactly(interpolation):
+    """A state field linear in space is linear along the straight stencils of a
+    regular mesh; every sub-stencil quadratic is then exact, so the left and right
+    midpoint states equal the field at the edge midpoint in both interpolation
+    modes (the characteristic projection is linear at its fixed frame)."""
+    m = make_mesh(10, L=1.0, periodic=False, seed=0, jitter=0.0, diag="uniform")
+    o = Oracle(m, deg=3, interpolation=interpolation)
+    a = np.array([1.0, 0.3, -0.2, 2.5])
+    B = np.array([[0.05, -0.02], [0.01, 0.03], [-0.02, 0.01], [0.04, 0.02]])
+    w = torch.from_numpy(a[None, :] + m.xy @ B.T)
+    wL, wR = o.edge_states(w)
+    mid = torch.from_numpy(a[None, :] + o.edge_midpoints() @ B.T)
+    # stencils that stay straight (near the boundary the continuation turns)
+    P = m.xy[o.sten6]                                            # [ne, 6, 2]
+    d = P[:, 3] - P[:, 2]
+    rel = P - P[:, 2:3]
+    interior = np.all(np.abs(rel[..., 0] * d[:, None, 1] - rel[..., 1] * d[:, None, 0]) < 1e-12, 1)
+    assert interior.sum() > 50
+    assert float((wL - mid)[interior].abs().max()) < 1e-13
+    assert float((wR - mid)[interior].abs().max()) < 1e-13
