@@ -109,7 +109,15 @@ void fdu_default_params(fdu_params* out);
  *   nv_total - nv_real; periodic != 0 wraps displacements to the nearest image
  *   in the box Lx x Ly.  deg = polynomial degree (3..6), level = 0 (automatic:
  *   one-level for deg <= 3, two-level otherwise), 1 or 2; reorder = 0 natural,
- *   1 reverse Cuthill-McKee, 2 Hilbert curve through the vertex coordinates.  nthreads <= 0 uses all host cores.
+ *   1 reverse Cuthill-McKee, 2 Hilbert curve through the vertex coordinates.
+ *   nthreads <= 0 uses all host cores.  artificial != 0 (Sec. 2.2.2): a real
+ *   vertex whose one-level stencil has fewer than deg(deg+3)+4 conditions is
+ *   joined by artificial edges to the far vertex of the triangle across each of
+ *   its ring edges (when not yet a neighbour), and those vertices and edges join
+ *   its one-level stencil (two-level only if still short).  Artificial edges get
+ *   input edge ids ne, ne+1, ... in lexicographic order of their end ids; the
+ *   neighbour graph used for two-level stencils and for 1D stencil continuation
+ *   stays that of the input edges.
  * Errors: FDU_ERR_INVALID_ARG for inconsistent sizes or ids, FDU_ERR_NUMERIC
  * when an edge has no admissible stencil continuation or a least-squares
  * matrix is rank deficient.
@@ -133,12 +141,15 @@ typedef struct {
   const double* hmin;        /* [nv_real] shortest incident edge */
   const int32_t* ghost_src;  /* [ng] new ids of the ghost sources */
   const int8_t* ghost_refl;  /* [ng] */
+  int64_t n_artificial;      /* artificial edges (input edge ids ne .. ne + n - 1) */
+  const int32_t* artificial; /* [n_artificial][2] their input end ids (a < b) */
 } fdu_prep_view;
 
 fdu_status fdu_prep_build(fdu_prep** out, int64_t nv_total, int64_t nv_real, const double* xy,
                           int64_t ne, const int32_t* edges, int64_t nt, const int32_t* tris,
                           const int32_t* ghost_src, const int8_t* ghost_refl, int periodic,
-                          double Lx, double Ly, int deg, int level, int reorder, int nthreads);
+                          double Lx, double Ly, int deg, int level, int reorder, int nthreads,
+                          int artificial);
 fdu_status fdu_prep_view_get(const fdu_prep* prep, fdu_prep_view* out);
 void fdu_prep_destroy(fdu_prep* prep);
 

@@ -16,9 +16,16 @@ Stencils:
   one-level  vertices N(O); edges of the triangles incident to O (spokes + ring).
   two-level  union of the one-level stencils of O and of every J in N(O),
              without O itself (18 vertices and 42 edges on a regular mesh).
-Reading (the paper allows artificial edges when a one-level stencil is short;
-this build adds none): a one-level stencil with fewer than deg(deg+3)+4
-conditions is replaced by the two-level one.
+Short one-level stencils (fewer than deg(deg+3)+4 conditions; the paper only
+says "not enough edges").  Default reading: replace it by the two-level one.
+With artificial edges (Sec. 2.2.2, figures of the one-level stencils with
+dashed edges): O is joined to the far vertex K of the triangle across each of
+its ring edges (J_a, J_b) when K is not yet a neighbour of O; those K and the
+new edges O-K join O's one-level stencil, and only if that is still short is
+the two-level stencil used.  Artificial edges get ids after the mesh's edges,
+in lexicographic order of their (smaller, larger) end ids; the neighbour graph
+(and so every two-level stencil and every edge's 1D stencil continuation) is
+that of the mesh's own edges.
 """
 from __future__ import annotations
 
@@ -81,6 +88,22 @@ class Topology:
         edges = set(int(x) for x in self.tri_edges[self.tris(O)].reshape(-1))
         return verts, edges
 
+    def across_vertices(self, O):
+        """Far vertex of the triangle on the other side of each ring edge of O
+        (ring edge = side of a triangle at O not touching O), when it is not O
+        itself or a neighbour of O."""
+        t = self.mesh.tri
+        nb = set(int(x) for x in self.nbrs(O))
+        out = set()
+        for tr in self.tris(O):
+            a, b = [int(x) for x in t[tr] if x != O]
+            other = (set(int(x) for x in self.tris(a)) & set(int(x) for x in self.tris(b))) - {int(tr)}
+            for to in other:
+                K = [int(x) for x in t[to] if x != a and x != b][0]
+                if K != O and K not in nb:
+                    out.add(K)
+        return out
+
     def two_level(self, O):
         verts, edges = set(), set()
         for J in [O] + [int(x) for x in self.nbrs(O)]:
@@ -91,12 +114,35 @@ class Topology:
         return verts, edges
 
 
-def divergence_stencil(topo: Topology, O: int, deg: int, level=None):
-    """Sorted (vertex ids, edge ids) of the divergence stencil of O."""
+def artificial_edges(topo: Topology, vertices, deg: int, level=None) -> np.ndarray:
+    """[n, 2] artificial edges (smaller id first, lexicographic order) that the
+    one-level stencils of the given real vertices need."""
+    if level is None:
+        level = 2 if deg > 3 else 1
+    pairs = set()
+    if level == 1:
+        for O in vertices:
+            O = int(O)
+            v, e = topo.one_level(O)
+            if 2 * len(v) + len(e) < conditions_needed(deg) + 4:
+                for K in topo.across_vertices(O):
+                    pairs.add((min(O, K), max(O, K)))
+    return np.array(sorted(pairs), dtype=np.int64).reshape(-1, 2)
+
+
+def divergence_stencil(topo: Topology, O: int, deg: int, level=None, art=None):
+    """Sorted (vertex ids, edge ids) of the divergence stencil of O.  art: the
+    artificial edges (array [n, 2], ids topo's edge count + row), or None."""
     if level is None:
         level = 2 if deg > 3 else 1
     if level == 1:
         v, e = topo.one_level(O)
+        if 2 * len(v) + len(e) < conditions_needed(deg) + 4 and art is not None and len(art):
+            ne = len(topo.ekey)
+            for K in topo.across_vertices(O):
+                row = np.nonzero((art[:, 0] == min(O, K)) & (art[:, 1] == max(O, K)))[0]
+                v.add(K)
+                e.add(ne + int(row[0]))
         if 2 * len(v) + len(e) < conditions_needed(deg) + 4:
             v, e = topo.two_level(O)
     else:
@@ -135,9 +181,11 @@ def mean_incident_length(mesh, topo: Topology, O: int) -> float:
     return float(np.sqrt((d * d).sum(-1)).mean())
 
 
-def ls_weights(mesh, topo: Topology, vertices, deg: int, level=None):
+def ls_weights(mesh, topo: Topology, vertices, deg: int, level=None, art=None):
     """Divergence weights of the given vertices as CSR arrays:
     vptr, vcol, wf, wg (vertex part) and eptr, ecol, we (edge part).
+    With artificial edges (art), mesh.edges must list the mesh's edges followed
+    by them.
 
     The weight row is r_a1 + r_b2 of the SVD pseudo-inverse
     A^+ = V diag(1/sigma) U^T (zero for sigma < RANK_TOL sigma_max), divided
@@ -145,7 +193,7 @@ def ls_weights(mesh, topo: Topology, vertices, deg: int, level=None):
     exps = monomial_exponents(deg)
     M = len(exps)
     vertices = np.asarray(vertices, dtype=np.int64)
-    sten = [divergence_stencil(topo, int(O), deg, level) for O in vertices]
+    sten = [divergence_stencil(topo, int(O), deg, level, art) for O in vertices]
     hO = np.array([mean_incident_length(mesh, topo, int(O)) for O in vertices])
     nV = np.array([len(v) for v, _ in sten], dtype=np.int64)
     nE = np.array([len(e) for _, e in sten], dtype=np.int64)

@@ -29,12 +29,14 @@ wall negated (parity unpinned).
 """
 from __future__ import annotations
 
+from dataclasses import replace
+
 import numpy as np
 import torch
 
 from . import euler
 from .geometry import arc_coordinates, min_image, neighbour_table, select_1d_stencils
-from .lsq import Topology, ls_weights
+from .lsq import Topology, artificial_edges, ls_weights
 from .nuweno import NUWeno5, WENO_EPS, WENO_POWER, uniform_weno5
 
 
@@ -42,7 +44,7 @@ class Oracle:
     def __init__(self, mesh, deg: int = 5, level=None, vertices=None, gamma: float = euler.GAMMA,
                  weno_eps: float = WENO_EPS, weno_power: int = WENO_POWER,
                  entropy_frac: float = 0.1, riemann: str = "roe", positivity: bool = True,
-                 interpolation: str = "characteristic", weno: str = "nonuniform"):
+                 interpolation: str = "characteristic", weno: str = "nonuniform", artificial: bool = False):
         if interpolation not in ("characteristic", "conservative") or weno not in ("nonuniform", "uniform"):
             raise ValueError("interpolation: characteristic|conservative, weno: nonuniform|uniform")
         self.interpolation = interpolation
@@ -57,10 +59,16 @@ class Oracle:
         if np.any(self.vertices >= mesh.nv_real):
             raise ValueError("residuals are defined on real vertices only")
         self.topo = Topology(mesh)
-        self.W = ls_weights(mesh, self.topo, self.vertices, deg, level)
+        # artificial edges (all real vertices decide, so a subset of vertices sees
+        # the same edge ids as the whole mesh); the edge list becomes mesh + them
+        self.artificial = (artificial_edges(self.topo, np.arange(mesh.nv_real), deg, level) if artificial
+                           else np.zeros((0, 2), np.int64))
+        self.all_edges = np.concatenate([mesh.edges.astype(np.int64), self.artificial], 0)
+        mesh_e = replace(mesh, edges=self.all_edges)
+        self.W = ls_weights(mesh_e, self.topo, self.vertices, deg, level, self.artificial if artificial else None)
         self.edges = np.unique(self.W["ecol"])                      # edges whose flux is needed
-        nbtab, _ = neighbour_table(mesh)
-        self.sten6 = select_1d_stencils(mesh, self.edges, nbtab)
+        nbtab, _ = neighbour_table(mesh)                             # continuation along the mesh's edges
+        self.sten6 = select_1d_stencils(mesh_e, self.edges, nbtab)
         self.s, self.dir = arc_coordinates(mesh, self.sten6)
         if weno == "uniform":        # standard WENO5 whatever the node spacing (Sec. 2.3.2 comparison)
             self.wenoL = uniform_weno5(len(self.edges), weno_eps, weno_power)

@@ -42,7 +42,8 @@ fdu_status guard(F&& f) {
 
 struct fdu_prep {
   int64_t nv_total = 0, nv_real = 0, ne_flux = 0, nnz_v = 0, nnz_e = 0;
-  std::vector<int32_t> perm, iperm, flux_edge, sten6, vptr, vcol, eptr, ecol, ghost_src;
+  int64_t n_artificial = 0;
+  std::vector<int32_t> perm, iperm, flux_edge, sten6, vptr, vcol, eptr, ecol, ghost_src, artificial;
   std::vector<int8_t> ghost_refl;
   std::vector<double> geo, wfg, we, hmin;
 };

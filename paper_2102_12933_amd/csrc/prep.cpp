@@ -115,6 +115,11 @@ struct Mesh {
   std::vector<int32_t> vt_col;
   std::vector<int32_t> tri_edge; // [nt][3]
   std::vector<int32_t> v_edge;   // vertex -> incident edge ids, aligned with nb_col
+  // artificial edges: ids ne .. ne + na - 1, appended to the edge list
+  bool use_artificial = false;
+  int64_t na = 0;
+  std::vector<int32_t> all_edges;   // [ne + na][2] when artificial edges exist
+  std::vector<int64_t> art_key;     // sorted (a * nv + b) of the artificial edges
 
   void build() {
     std::vector<int64_t> deg(nv, 0);
@@ -166,6 +171,37 @@ struct Mesh {
         if (e < 0) throw Error(FDU_ERR_INVALID_ARG, "a triangle side is not in the edge list");
         tri_edge[3 * t + k] = e;
       }
+  }
+  // Far vertex of the triangle across each ring edge of O (a triangle side at
+  // O not touching O), when it is neither O nor a neighbour of O.
+  void across_vertices(int32_t O, std::vector<int32_t>& out) const {
+    out.clear();
+    for (int64_t i = vt_ptr[O]; i < vt_ptr[O + 1]; ++i) {
+      const int32_t t = vt_col[i];
+      int32_t ab[2], n = 0;
+      for (int k = 0; k < 3; ++k)
+        if (tris[3 * t + k] != O && n < 2) ab[n++] = tris[3 * t + k];
+      if (n != 2) continue;
+      for (int64_t j = vt_ptr[ab[0]]; j < vt_ptr[ab[0] + 1]; ++j) {
+        const int32_t u = vt_col[j];
+        if (u == t) continue;
+        int32_t K = -1;
+        bool has_b = false;
+        for (int k = 0; k < 3; ++k) {
+          const int32_t x = tris[3 * u + k];
+          if (x == ab[1]) has_b = true;
+          else if (x != ab[0]) K = x;
+        }
+        if (!has_b || K < 0 || K == O || edge_between(O, K) >= 0) continue;
+        if (std::find(out.begin(), out.end(), K) == out.end()) out.push_back(K);
+      }
+    }
+  }
+  int32_t artificial_id(int32_t a, int32_t b) const {
+    const int64_t key = (int64_t)std::min(a, b) * nv + std::max(a, b);
+    auto it = std::lower_bound(art_key.begin(), art_key.end(), key);
+    if (it == art_key.end() || *it != key) return -1;
+    return (int32_t)(ne + (it - art_key.begin()));
   }
   int32_t edge_between(int32_t a, int32_t b) const {
     const int32_t* beg = nb_col.data() + nb_ptr[a];
@@ -286,7 +322,20 @@ void divergence_stencil(const Mesh& m, int32_t O, int deg, int level, std::vecto
     E.clear();
     tri_edges_of(O, E);
     uniq(E);
-    if ((int64_t)(2 * V.size() + E.size()) < (int64_t)deg * (deg + 3) + 4) two_level();
+    const int64_t need = (int64_t)deg * (deg + 3) + 4;
+    if ((int64_t)(2 * V.size() + E.size()) < need && m.use_artificial) {
+      std::vector<int32_t> K;
+      m.across_vertices(O, K);
+      for (int32_t k : K) {
+        const int32_t id = m.artificial_id(O, k);
+        if (id < 0) throw Error(FDU_ERR_NUMERIC, "artificial edge missing from the list");
+        V.push_back(k);
+        E.push_back(id);
+      }
+      uniq(V);
+      uniq(E);
+    }
+    if ((int64_t)(2 * V.size() + E.size()) < need) two_level();
   } else {
     two_level();
   }
@@ -546,7 +595,8 @@ using namespace fdu;
 extern "C" fdu_status fdu_prep_build(fdu_prep** out, int64_t nv_total, int64_t nv_real, const double* xy,
                                      int64_t ne, const int32_t* edges, int64_t nt, const int32_t* tris,
                                      const int32_t* ghost_src, const int8_t* ghost_refl, int periodic,
-                                     double Lx, double Ly, int deg, int level, int reorder, int nthreads) {
+                                     double Lx, double Ly, int deg, int level, int reorder, int nthreads,
+                                     int artificial) {
   return guard([&] {
     if (!out || !xy || !edges || !tris) throw Error(FDU_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
@@ -569,6 +619,38 @@ extern "C" fdu_status fdu_prep_build(fdu_prep** out, int64_t nv_total, int64_t n
     m.sp = Space{xy, periodic != 0, Lx, Ly};
     m.edges = edges; m.tris = tris;
     m.build();
+    if (artificial) {
+      // artificial edges for the short one-level stencils (ids after the mesh's edges)
+      const int lvl = level == 0 ? (deg > 3 ? 2 : 1) : level;
+      std::vector<int64_t> keys;
+      if (lvl == 1) {
+        std::vector<int32_t> E, K;
+        for (int64_t O = 0; O < nv_real; ++O) {
+          E.clear();
+          for (int64_t i = m.vt_ptr[O]; i < m.vt_ptr[O + 1]; ++i)
+            for (int k = 0; k < 3; ++k) E.push_back(m.tri_edge[3 * m.vt_col[i] + k]);
+          std::sort(E.begin(), E.end());
+          E.erase(std::unique(E.begin(), E.end()), E.end());
+          const int64_t cond = 2 * (m.nb_ptr[O + 1] - m.nb_ptr[O]) + (int64_t)E.size();
+          if (cond >= (int64_t)deg * (deg + 3) + 4) continue;
+          m.across_vertices((int32_t)O, K);
+          for (int32_t k : K) keys.push_back(std::min<int64_t>(O, k) * nv_total + std::max<int64_t>(O, k));
+        }
+      }
+      std::sort(keys.begin(), keys.end());
+      keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+      if (ne + (int64_t)keys.size() >= INT32_MAX) throw Error(FDU_ERR_INVALID_ARG, "too many edges for 32-bit ids");
+      m.art_key = keys;
+      m.na = (int64_t)keys.size();
+      m.all_edges.assign(edges, edges + 2 * ne);
+      for (int64_t key : keys) {
+        m.all_edges.push_back((int32_t)(key / nv_total));
+        m.all_edges.push_back((int32_t)(key % nv_total));
+      }
+      m.edges = m.all_edges.data();
+      m.use_artificial = true;
+    }
+    const int64_t ne_all = ne + m.na;
 
     auto P = new fdu_prep();
     std::unique_ptr<fdu_prep> hold(P);
@@ -595,19 +677,19 @@ extern "C" fdu_status fdu_prep_build(fdu_prep** out, int64_t nv_total, int64_t n
     });
 
     // flux edges: every edge a divergence stencil uses, ordered by new end ids
-    std::vector<char> need(ne, 0);
+    std::vector<char> need(ne_all, 0);
     for (auto& r : rows)
       for (int32_t e : r.E) need[e] = 1;
     std::vector<int32_t> fe;
-    for (int64_t e = 0; e < ne; ++e)
+    for (int64_t e = 0; e < ne_all; ++e)
       if (need[e]) fe.push_back((int32_t)e);
     auto key = [&](int32_t e) {
-      int32_t a = iperm[edges[2 * e]], b = iperm[edges[2 * e + 1]];
+      int32_t a = iperm[m.edges[2 * e]], b = iperm[m.edges[2 * e + 1]];
       return std::make_pair(std::min(a, b), std::max(a, b));
     };
     std::sort(fe.begin(), fe.end(), [&](int32_t x, int32_t y) { return key(x) < key(y); });
     const int64_t nf = (int64_t)fe.size();
-    std::vector<int32_t> floc(ne, -1);
+    std::vector<int32_t> floc(ne_all, -1);
     for (int64_t i = 0; i < nf; ++i) floc[fe[i]] = (int32_t)i;
     P->ne_flux = nf;
     P->flux_edge = fe;
@@ -679,6 +761,8 @@ extern "C" fdu_status fdu_prep_build(fdu_prep** out, int64_t nv_total, int64_t n
       P->ghost_src[g] = iperm[ghost_src[g]];
       P->ghost_refl[g] = ghost_refl[g];
     }
+    P->n_artificial = m.na;
+    P->artificial.assign(m.all_edges.begin() + (m.na ? 2 * ne : 0), m.all_edges.end());
     P->perm = std::move(perm);
     P->iperm = std::move(iperm);
     *out = hold.release();
@@ -707,6 +791,8 @@ extern "C" fdu_status fdu_prep_view_get(const fdu_prep* p, fdu_prep_view* v) {
     v->hmin = p->hmin.data();
     v->ghost_src = p->ghost_src.data();
     v->ghost_refl = p->ghost_refl.data();
+    v->n_artificial = p->n_artificial;
+    v->artificial = p->artificial.data();
   });
 }
 

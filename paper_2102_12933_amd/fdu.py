@@ -38,14 +38,15 @@ class PrepView(C.Structure):
                 ("perm", C.c_void_p), ("iperm", C.c_void_p), ("flux_edge", C.c_void_p),
                 ("sten6", C.c_void_p), ("geo", C.c_void_p), ("vptr", C.c_void_p), ("vcol", C.c_void_p),
                 ("wfg", C.c_void_p), ("eptr", C.c_void_p), ("ecol", C.c_void_p), ("we", C.c_void_p),
-                ("hmin", C.c_void_p), ("ghost_src", C.c_void_p), ("ghost_refl", C.c_void_p)]
+                ("hmin", C.c_void_p), ("ghost_src", C.c_void_p), ("ghost_refl", C.c_void_p),
+                ("n_artificial", C.c_int64), ("artificial", C.c_void_p)]
 
 
 P, I64, I32, D, VP = C.POINTER, C.c_int64, C.c_int, C.c_double, C.c_void_p
 _SIGS = {
     "fdu_last_error": (C.c_char_p, []),
     "fdu_default_params": (None, [P(Params)]),
-    "fdu_prep_build": (I32, [P(VP), I64, I64, VP, I64, VP, I64, VP, VP, VP, I32, D, D, I32, I32, I32, I32]),
+    "fdu_prep_build": (I32, [P(VP), I64, I64, VP, I64, VP, I64, VP, VP, VP, I32, D, D, I32, I32, I32, I32, I32]),
     "fdu_prep_view_get": (I32, [VP, P(PrepView)]),
     "fdu_prep_destroy": (None, [VP]),
     "fdu_create": (I32, [P(VP), I32, I32, P(Params)]),
@@ -124,9 +125,10 @@ def default_params(**kw) -> Params:
 class Prep:
     """Host preprocessing of a mesh (C++ inside libfdu)."""
 
-    def __init__(self, mesh, deg: int = 5, level: int = 0, reorder: int = 1, nthreads: int = 0):
+    def __init__(self, mesh, deg: int = 5, level: int = 0, reorder: int = 1, nthreads: int = 0,
+                 artificial: bool = False):
         self.mesh = mesh
-        self.deg, self.level, self.reorder = deg, level, reorder
+        self.deg, self.level, self.reorder, self.artificial = deg, level, reorder, artificial
         xy = np.ascontiguousarray(mesh.xy, np.float64)
         edges = np.ascontiguousarray(mesh.edges, np.int32)
         tris = np.ascontiguousarray(mesh.tri, np.int32)
@@ -137,7 +139,8 @@ class Prep:
               _ptr(edges, np.int32), tris.shape[0], _ptr(tris, np.int32),
               gs.ctypes.data_as(C.c_void_p) if gs.size else None,
               gr.ctypes.data_as(C.c_void_p) if gr.size else None,
-              int(mesh.periodic), float(mesh.box[0]), float(mesh.box[1]), deg, level, reorder, nthreads)
+              int(mesh.periodic), float(mesh.box[0]), float(mesh.box[1]), deg, level, reorder, nthreads,
+              int(bool(artificial)))
         self.handle = h
         v = PrepView()
         _call("fdu_prep_view_get", h, C.byref(v))
@@ -164,7 +167,8 @@ class Prep:
             wfg=arr(v.wfg, 2 * nzv, C.c_double, np.float64).reshape(nzv, 2),
             eptr=arr(v.eptr, nvr + 1, C.c_int32, np.int64), ecol=arr(v.ecol, nze, C.c_int32, np.int64),
             we=arr(v.we, nze, C.c_double, np.float64), hmin=arr(v.hmin, nvr, C.c_double, np.float64),
-            ghost_src=arr(v.ghost_src, ng, C.c_int32, np.int64), ghost_refl=arr(v.ghost_refl, ng, C.c_int8, np.int8))
+            ghost_src=arr(v.ghost_src, ng, C.c_int32, np.int64), ghost_refl=arr(v.ghost_refl, ng, C.c_int8, np.int8),
+            artificial=arr(v.artificial, 2 * v.n_artificial, C.c_int32, np.int64).reshape(-1, 2))
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

@@ -31,16 +31,21 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(fdu.exported_symbols())
 
 
-CASES = [(33, True, 0, 3, 1), (33, True, 0, 5, 1), (18, False, 4, 5, 0), (18, False, 4, 5, 1),
-         (65, False, 4, 5, 1),   # 65^2 seed 3 and 0: mirror-ghost corners with rank-deficient systems
-         (33, True, 0, 5, 2), (18, False, 4, 5, 2)]   # Hilbert order
+CASES = [(33, True, 0, 3, 1, False), (33, True, 0, 5, 1, False), (18, False, 4, 5, 0, False),
+         (18, False, 4, 5, 1, False),
+         (65, False, 4, 5, 1, False),   # 65^2 seed 3 and 0: mirror-ghost corners with rank-deficient systems
+         (33, True, 0, 5, 2, False), (18, False, 4, 5, 2, False),    # Hilbert order
+         (33, True, 0, 3, 1, True), (18, False, 4, 3, 2, True)]      # artificial edges
 
 
-@pytest.mark.parametrize("N,periodic,ghosts,deg,reorder", CASES)
-def test_prep_matches_oracle(N, periodic, ghosts, deg, reorder):
+@pytest.mark.parametrize("N,periodic,ghosts,deg,reorder,artificial", CASES)
+def test_prep_matches_oracle(N, periodic, ghosts, deg, reorder, artificial):
     m = make_mesh(N, L=10.0 if periodic else 1.0, periodic=periodic, seed=3, ghost_layers=ghosts)
-    A = fdu.Prep(m, deg=deg, reorder=reorder).arrays()
-    o = Oracle(m, deg=deg)
+    A = fdu.Prep(m, deg=deg, reorder=reorder, artificial=artificial).arrays()
+    o = Oracle(m, deg=deg, artificial=artificial)
+    np.testing.assert_array_equal(A["artificial"], o.artificial)
+    if artificial:
+        assert len(o.artificial) > 0
     perm = A["perm"]
     assert np.array_equal(np.sort(perm[:m.nv_real]), np.arange(m.nv_real))
     assert np.array_equal(perm[A["iperm"]], np.arange(m.nv))

@@ -38,11 +38,11 @@ def perturbed_sod(m, seed=0, amp=0.05):
 
 
 class Case:
-    def __init__(self, N, periodic, ghosts, deg, state, reorder=1, seed=0, **params):
+    def __init__(self, N, periodic, ghosts, deg, state, reorder=1, seed=0, artificial=False, **params):
         fdu = _fdu()
         L = 10.0 if periodic else 1.0
         self.m = make_mesh(N, L=L, periodic=periodic, seed=seed, ghost_layers=ghosts)
-        self.prep = fdu.Prep(self.m, deg=deg, reorder=reorder)
+        self.prep = fdu.Prep(self.m, deg=deg, reorder=reorder, artificial=artificial)
         self.A = self.prep.arrays()
         self.perm = self.A["perm"]
         self.s = fdu.Solver(self.prep, device=0, **params)
@@ -57,7 +57,7 @@ class Case:
             okw["interpolation"] = "conservative"
         if params.get("uniform_weno"):
             okw["weno"] = "uniform"
-        self.o = Oracle(self.m, deg=deg, **okw)
+        self.o = Oracle(self.m, deg=deg, artificial=artificial, **okw)
         self.w0 = vortex_state(self.m, beta=5.0, mach=0.5) if state == "vortex" else perturbed_sod(self.m)
 
     def w_dev(self, w=None):
@@ -307,6 +307,17 @@ def test_hilbert_order_variants(vertex):
     """Hilbert vertex order (compact vertex blocks for the LDS-staged variants):
     residual and one RK stage against the oracle, walled and periodic meshes."""
     for c in (Case(33, True, 0, 5, "vortex", reorder=2), Case(20, False, 4, 5, "sod", reorder=2)):
+        c.s.set_variants(1, vertex)
+        err = _residual_err(c)
+        assert err.max() <= TOL, err.max()
+
+
+@pytest.mark.parametrize("vertex", [0, 3, 10])
+def test_artificial_edges_residual_and_stage(vertex):
+    """Degree-3 one-level stencils completed with artificial edges (Sec. 2.2.2):
+    residual and one RK stage against the oracle built the same way."""
+    for c in (Case(33, True, 0, 3, "vortex", artificial=True), Case(20, False, 4, 3, "sod", reorder=2, artificial=True)):
+        assert len(c.A["artificial"]) > 0
         c.s.set_variants(1, vertex)
         err = _residual_err(c)
         assert err.max() <= TOL, err.max()

@@ -106,11 +106,13 @@ def test_ls_weights_minimum_norm_on_two_level():
     np.testing.assert_allclose(Q @ (Q.T @ rho), rho, atol=1e-10 * np.abs(rho).max())
 
 
-@pytest.mark.parametrize("deg", [3, 5])
-def test_divergence_exact_for_polynomials(deg):
+@pytest.mark.parametrize("deg,artificial", [(3, False), (5, False), (3, True)])
+def test_divergence_exact_for_polynomials(deg, artificial):
     m = make_mesh(16, L=1.0, periodic=False, seed=5, ghost_layers=4)
     verts = np.arange(0, m.nv_real, 3)
-    o = Oracle(m, deg=deg, vertices=verts)
+    o = Oracle(m, deg=deg, vertices=verts, artificial=artificial)
+    if artificial:
+        assert len(o.artificial) > 0 and np.any(o.edges >= len(m.edges))
     rng = np.random.default_rng(deg)
     cf, cg = rng.normal(size=(deg + 1, deg + 1)), rng.normal(size=(deg + 1, deg + 1))
     for i in range(deg + 1):
@@ -272,3 +274,34 @@ def test_linear_fields_interpolated_exactly(interpolation):
     assert interior.sum() > 50
     assert float((wL - mid)[interior].abs().max()) < 1e-13
     assert float((wR - mid)[interior].abs().max()) < 1e-13
+
+
+def test_artificial_edges_on_valence_four_vertices():
+    """A valence-4 vertex of a triangulation (the paper's one-level stencil with
+    only 4 direct neighbours) has 4 vertices and 8 edges, 16 conditions: too
+    few for degree 3.  Artificial edges join it to the far vertex of the triangle
+    across each of its 4 ring edges, giving 8 vertices and 12 edges (28
+    conditions), so it keeps a one-level stencil."""
+    from oracle.lsq import Topology, artificial_edges, divergence_stencil
+    m = make_mesh(24, L=1.0, periodic=True, seed=11)
+    topo = Topology(m)
+    val = np.diff(topo.nb_ptr)[:m.nv_real]
+    v4 = np.nonzero(val == 4)[0]
+    assert len(v4) > 5
+    art = artificial_edges(topo, np.arange(m.nv_real), 3)
+    ne = len(m.edges)
+    for O in v4[:10]:
+        O = int(O)
+        mine = art[(art[:, 0] == O) | (art[:, 1] == O)]
+        V, E = divergence_stencil(topo, O, 3, 1, art)
+        assert len(V) == 8 and len(E) == 12, (O, len(V), len(E))
+        assert np.sum(E >= ne) == 4
+        K = set(int(x) for x in mine.reshape(-1)) - {O}
+        assert len(K) >= 4 and set(int(v) for v in V) >= set(int(x) for x in topo.nbrs(O))
+        # every artificial edge of O crosses one of O's ring edges: K is 2 edges away
+        for k in K:
+            assert k not in set(int(x) for x in topo.nbrs(O))
+            assert len(set(int(x) for x in topo.nbrs(k)) & set(int(x) for x in topo.nbrs(O))) >= 2
+    # without artificial edges those vertices fall back to the two-level stencil
+    V2, E2 = divergence_stencil(topo, int(v4[0]), 3, 1, None)
+    assert len(E2) > 20
