@@ -105,9 +105,10 @@ void fdu_default_params(fdu_params* out);
  * Inputs (host, read only during the call):
  *   xy [nv_total][2] double; edges [ne][2] int32 (a < b); tris [nt][3] int32;
  *   ghost_src [ng] int32 (source real vertex of ghost nv_real+i),
- *   ghost_refl [ng] int8 (bit 0: negate m_x, bit 1: negate m_y); ng =
- *   nv_total - nv_real; periodic != 0 wraps displacements to the nearest image
- *   in the box Lx x Ly.  deg = polynomial degree (3..6), level = 0 (automatic:
+ *   ghost_refl [ng] int8 (bit 0: negate m_x, bit 1: negate m_y, bit 2:
+ *   Dirichlet ghost whose state is given, see fdu_upload_ghost_states); ng =
+ *   nv_total - nv_real; periodic = 1 wraps displacements to the nearest image
+ *   in the box Lx x Ly, 2 wraps y only (a channel with walls in x), 0 none.  deg = polynomial degree (3..6), level = 0 (automatic:
  *   one-level for deg <= 3, two-level otherwise), 1 or 2; reorder = 0 natural,
  *   1 reverse Cuthill-McKee, 2 Hilbert curve through the vertex coordinates.
  *   nthreads <= 0 uses all host cores.  artificial != 0 (Sec. 2.2.2): a real
@@ -161,6 +162,15 @@ void fdu_prep_destroy(fdu_prep* prep);
  * and CSR monotonicity and reject non-finite weights (FDU_ERR_INVALID_ARG).
  * fdu_upload_prep uploads everything a prep built.  fdu_finalize derives
  * the per-vertex sums c_O = sum_k we_k n_k and must precede compute calls.
+ * fdu_upload_ghost_states (Dirichlet boundaries, the paper's inflow/outflow
+ * conditions): states [ng][4] (host, conservative variables, library ghost
+ * order); the rows of ghosts flagged Dirichlet (bit 2) are the states those
+ * ghosts take at every ghost fill, other rows are ignored.  Required before
+ * fdu_finalize when Dirichlet ghosts exist; may be called again later to
+ * change the boundary values (same device buffer, so captured graphs see the
+ * new values).  Synchronous.  FDU_ERR_INVALID_ARG for a count mismatch or a
+ * non-finite or non-positive-density Dirichlet row.  The adjoint treats
+ * Dirichlet ghosts as constants.
  */
 typedef struct fdu_solver fdu_solver;
 
@@ -172,6 +182,7 @@ fdu_status fdu_upload_vertex_stencils(fdu_solver* s, const int32_t* vptr, const 
                                       const double* wfg, const int32_t* eptr, const int32_t* ecol,
                                       const double* we, const double* hmin);
 fdu_status fdu_upload_ghosts(fdu_solver* s, int64_t ng, const int32_t* ghost_src, const int8_t* ghost_refl);
+fdu_status fdu_upload_ghost_states(fdu_solver* s, int64_t ng, const double* states);
 fdu_status fdu_upload_prep(fdu_solver* s, const fdu_prep* prep);
 fdu_status fdu_finalize(fdu_solver* s);
 

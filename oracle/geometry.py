@@ -25,11 +25,16 @@ TIE_TOL = 1e-12
 
 
 def min_image(mesh, d: np.ndarray) -> np.ndarray:
-    """Displacement vectors d [..., 2] reduced to the nearest periodic image."""
-    if not mesh.periodic:
+    """Displacement vectors d [..., 2] reduced to the nearest periodic image
+    (mesh.periodic: True = both directions, "y" = y only, False = none)."""
+    if mesh.periodic is False or mesh.periodic is None:
         return d
     L = np.asarray(mesh.box, dtype=np.float64)
-    return d - L * np.round(d / L)
+    out = np.array(d, dtype=np.float64, copy=True)
+    if mesh.periodic == "y":
+        out[..., 1] -= L[1] * np.round(out[..., 1] / L[1])
+        return out
+    return out - L * np.round(out / L)
 
 
 def vec(mesh, a, b) -> np.ndarray:

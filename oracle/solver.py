@@ -21,6 +21,8 @@ Ablation switches (the comparisons of Sec. 2.3.1-2.3.2, defaults = the paper's
 scheme): ``interpolation="conservative"`` interpolates the conservative
 variables directly instead of the characteristic ones; ``weno="uniform"`` uses
 standard WENO5 (equally spaced nodes) whatever the spacing along the stencil.
+Dirichlet boundaries (the paper's inflow/outflow condition): ghosts flagged
+Dirichlet (bit 2 of ghost_refl) take given states (``ghost_state``).
 Readings: dt = CFL * min_v h_v / (|u_v| + c_v) over real vertices, h_v the
 shortest edge at v (the paper names the CFL number but no formula).  Walls (not
 in the paper, which has periodic and Dirichlet boundaries only): ghost states
@@ -44,10 +46,12 @@ class Oracle:
     def __init__(self, mesh, deg: int = 5, level=None, vertices=None, gamma: float = euler.GAMMA,
                  weno_eps: float = WENO_EPS, weno_power: int = WENO_POWER,
                  entropy_frac: float = 0.1, riemann: str = "roe", positivity: bool = True,
-                 interpolation: str = "characteristic", weno: str = "nonuniform", artificial: bool = False):
+                 interpolation: str = "characteristic", weno: str = "nonuniform", artificial: bool = False,
+                 ghost_state=None):
         if interpolation not in ("characteristic", "conservative") or weno not in ("nonuniform", "uniform"):
             raise ValueError("interpolation: characteristic|conservative, weno: nonuniform|uniform")
         self.interpolation = interpolation
+        self.ghost_state = None if ghost_state is None else torch.as_tensor(np.asarray(ghost_state, np.float64))
         self.mesh = mesh
         self.positivity = positivity
         self.gamma = gamma
@@ -100,6 +104,11 @@ class Oracle:
         sx = 1.0 - 2.0 * (refl & 1).to(w.dtype)
         sy = 1.0 - 2.0 * ((refl >> 1) & 1).to(w.dtype)
         g = torch.stack([g[:, 0], sx * g[:, 1], sy * g[:, 2], g[:, 3]], -1)
+        dirichlet = torch.from_numpy((m.ghost_refl & 4) != 0)
+        if bool(dirichlet.any()):                   # Dirichlet ghosts take the given states
+            if self.ghost_state is None:
+                raise ValueError("the mesh has Dirichlet ghosts: pass ghost_state")
+            g = torch.where(dirichlet[:, None], self.ghost_state.to(w.dtype), g)
         return torch.cat([w[:m.nv_real], g], 0)
 
     # ---------------------------------------------------------------- edges

@@ -28,6 +28,7 @@ struct BatchInst {
   const double* hmin;
   const int* gsrc;
   const signed char* grefl;
+  const double* gstate;   // Dirichlet ghost states ([ng][4]) or null
   const int* vblk;   // vertex blocks of the LDS-staged vertex step
   const int* vb_uvp;
   const int* vb_uv;
@@ -121,10 +122,7 @@ __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict
       const int g = local * 256 + threadIdx.x;
       if (g < I.ng) {
         double q[4];
-        load4(wprev, I.gsrc[g], q);
-        const int f = I.grefl[g];
-        if (f & 1) q[1] = -q[1];
-        if (f & 2) q[2] = -q[2];
+        ghost_state<double>(wprev, g, I.gsrc, I.grefl, I.gstate, q);
         store4(wprev, I.nv_real + g, q);
       }
       if (phase < 0) signal_count(&ctr[1 + i]);

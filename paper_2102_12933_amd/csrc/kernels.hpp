@@ -411,15 +411,27 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // ----------------------------------------------------------------------------
 // Kernels.
 template <class T>
+__device__ __forceinline__ void ghost_state(const T* __restrict__ w, int g, const int* __restrict__ src,
+                                            const signed char* __restrict__ refl,
+                                            const double* __restrict__ gstate, double q[4]) {
+  const int f = refl[g];
+  if (f & 4) {          // Dirichlet: the given boundary state
+    load4(gstate, g, q);
+    return;
+  }
+  load4(w, src[g], q);  // mirror copy, reflecting walls negate the normal momentum
+  if (f & 1) q[1] = -q[1];
+  if (f & 2) q[2] = -q[2];
+}
+
+template <class T>
 __global__ void __launch_bounds__(256) k_fill_ghosts(T* __restrict__ w, int nreal, int ng, const int* __restrict__ src,
-                                                     const signed char* __restrict__ refl) {
+                                                     const signed char* __restrict__ refl,
+                                                     const double* __restrict__ gstate) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ng) return;
   double q[4];
-  load4(w, src[g], q);
-  const int f = refl[g];
-  if (f & 1) q[1] = -q[1];
-  if (f & 2) q[2] = -q[2];
+  ghost_state<T>(w, g, src, refl, gstate, q);
   store4(w, nreal + g, q);
 }
 

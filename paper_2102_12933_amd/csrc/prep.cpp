@@ -49,18 +49,17 @@ void parallel_for(int64_t n, int nthreads, F&& body) {
     if (e) std::rethrow_exception(e);
 }
 
-// Displacements with optional periodic wrap to the nearest image.
+// Displacements with optional periodic wrap to the nearest image
+// (mode 0: none, 1: both directions, 2: y only).
 struct Space {
   const double* xy;
-  bool periodic;
+  int mode;
   double Lx, Ly;
   void d(int64_t a, int64_t b, double& dx, double& dy) const {
     dx = xy[2 * b] - xy[2 * a];
     dy = xy[2 * b + 1] - xy[2 * a + 1];
-    if (periodic) {
-      dx -= Lx * std::nearbyint(dx / Lx);
-      dy -= Ly * std::nearbyint(dy / Ly);
-    }
+    if (mode == 1) dx -= Lx * std::nearbyint(dx / Lx);
+    if (mode != 0) dy -= Ly * std::nearbyint(dy / Ly);
   }
 };
 
@@ -606,6 +605,7 @@ extern "C" fdu_status fdu_prep_build(fdu_prep** out, int64_t nv_total, int64_t n
     if (deg < 1 || deg > 6) throw Error(FDU_ERR_INVALID_ARG, "deg must be in 1..6");
     if (level < 0 || level > 2) throw Error(FDU_ERR_INVALID_ARG, "level must be 0, 1 or 2");
     if (reorder < 0 || reorder > 2) throw Error(FDU_ERR_INVALID_ARG, "reorder must be 0, 1 or 2");
+    if (periodic < 0 || periodic > 2) throw Error(FDU_ERR_INVALID_ARG, "periodic must be 0, 1 or 2");
     if (periodic && (!(Lx > 0) || !(Ly > 0))) throw Error(FDU_ERR_INVALID_ARG, "periodic box must be positive");
     const int64_t ng = nv_total - nv_real;
     if (ng > 0 && (!ghost_src || !ghost_refl)) throw Error(FDU_ERR_INVALID_ARG, "ghost arrays required");
@@ -616,7 +616,7 @@ extern "C" fdu_status fdu_prep_build(fdu_prep** out, int64_t nv_total, int64_t n
 
     Mesh m;
     m.nv = nv_total; m.nreal = nv_real; m.ne = ne; m.nt = nt;
-    m.sp = Space{xy, periodic != 0, Lx, Ly};
+    m.sp = Space{xy, periodic, Lx, Ly};
     m.edges = edges; m.tris = tris;
     m.build();
     if (artificial) {

@@ -70,6 +70,8 @@ struct fdu_solver {
   DevBuf<float> te_w32, tv_wfg32;
   DevBuf<int32_t> sten, vptr, vcol, eptr, ecol, gsrc;
   DevBuf<int8_t> grefl;
+  DevBuf<double> gstate;     // [ng][4] Dirichlet ghost states (rows of other ghosts unused)
+  int64_t n_dirichlet = 0;
   DevBuf<double> geo, wfg, we, cO, hmin, flux, part;
   DevBuf<float> geo32, wfg32, we32;
   int cfl_blocks = 0;
@@ -172,7 +174,7 @@ void fill_ghosts_t(fdu_solver* s, T* w, hipStream_t st) {
   if (s->ng == 0) return;
   timed_launch(s, 0, st, [&] {
     hipLaunchKernelGGL(k_fill_ghosts<T>, dim3(nblocks(s->ng)), dim3(256), 0, st, w, (int)s->nv_real, (int)s->ng,
-                       s->gsrc.p, reinterpret_cast<const signed char*>(s->grefl.p));
+                       s->gsrc.p, reinterpret_cast<const signed char*>(s->grefl.p), s->gstate.p);
   });
   launch_check();
 }
@@ -378,13 +380,16 @@ void build_vertex_blocks(fdu_solver* s) {
 // stencils; entries of each list are in increasing order of their source index.
 void build_adjoint(fdu_solver* s) {
   const int64_t nv = s->nv_total, nr = s->nv_real, ne = s->ne_flux, ng = s->ng;
+  // CSR of the positions p grouped by keys[p] (negative keys are left out)
   auto csr = [](int64_t n, const std::vector<int32_t>& keys, std::vector<int32_t>& ptr, std::vector<int32_t>& ord) {
     ptr.assign(n + 1, 0);
-    for (int32_t k : keys) ptr[k + 1]++;
+    for (int32_t k : keys)
+      if (k >= 0) ptr[k + 1]++;
     for (int64_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
     std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
-    ord.assign(keys.size(), 0);
-    for (size_t p = 0; p < keys.size(); ++p) ord[fill[keys[p]]++] = (int32_t)p;
+    ord.assign(ptr[n], 0);
+    for (size_t p = 0; p < keys.size(); ++p)
+      if (keys[p] >= 0) ord[fill[keys[p]]++] = (int32_t)p;
   };
   std::vector<int32_t> ptr, ord, rowof;
   // edge -> (vertex O, we_Ok)
@@ -435,8 +440,12 @@ void build_adjoint(fdu_solver* s) {
   csr(nv, s->h_sten, ptr, ord);
   s->ts_ptr.upload(ptr.data(), ptr.size());
   s->ts_col.upload(ord.data(), ord.size());
-  // real vertex -> ghosts copied from it
-  csr(nr, s->h_gsrc, ptr, ord);
+  // real vertex -> ghosts copied from it (Dirichlet ghosts hold given states:
+  // no dependence on the solution, so they are left out)
+  std::vector<int32_t> gkey(s->h_gsrc);
+  for (size_t g = 0; g < gkey.size(); ++g)
+    if (s->h_grefl[g] & 4) gkey[g] = -1;
+  csr(nr, gkey, ptr, ord);
   s->tg_ptr.upload(ptr.data(), ptr.size());
   if (ord.empty()) ord.push_back(0);
   s->tg_col.upload(ord.data(), ord.size());
@@ -787,17 +796,40 @@ fdu_status fdu_upload_ghosts(fdu_solver* s, int64_t ng, const int32_t* ghost_src
     need(ng == s->ng, "ghost count must equal nv_total - nv_real");
     if (ng == 0) return;
     need(ghost_src && ghost_refl, "NULL ghost arrays");
+    int64_t nd = 0;
     for (int64_t i = 0; i < ng; ++i) {
       need(ghost_src[i] >= 0 && ghost_src[i] < s->nv_real, "ghost source must be a real vertex");
-      need((ghost_refl[i] & ~3) == 0, "ghost reflection flags must be in 0..3");
+      const int f = ghost_refl[i];
+      need((f & ~7) == 0 && !((f & 4) && (f & 3)), "ghost flags must be 0..3, or 4 (Dirichlet) alone");
+      nd += (f & 4) != 0;
     }
     DeviceGuard dg(s->device);
     s->finalized = false;
     s->adjoint = false;
+    s->n_dirichlet = nd;
+    s->gstate.release();
     s->gsrc.upload(ghost_src, ng);
     s->grefl.upload(ghost_refl, ng);
     s->h_gsrc.assign(ghost_src, ghost_src + ng);
     s->h_grefl.assign(ghost_refl, ghost_refl + ng);
+  });
+}
+
+fdu_status fdu_upload_ghost_states(fdu_solver* s, int64_t ng, const double* states) {
+  return guard([&] {
+    need(s != nullptr, "NULL solver");
+    need(ng == s->ng && s->grefl.n == (size_t)ng, "upload the ghosts first; ng must equal their count");
+    if (ng == 0) return;
+    need(states != nullptr, "NULL states");
+    for (int64_t g = 0; g < ng; ++g) {
+      if (!(s->h_grefl[g] & 4)) continue;
+      const double* q = states + 4 * g;
+      for (int k = 0; k < 4; ++k) need(std::isfinite(q[k]), "non-finite Dirichlet state");
+      need(q[0] > 0.0, "Dirichlet density must be positive");
+    }
+    DeviceGuard dg(s->device);
+    if (s->gstate.n != (size_t)(4 * ng)) s->gstate.alloc(4 * ng);   // keep the address for captured graphs
+    FDU_HIP(hipMemcpy(s->gstate.p, states, 4 * ng * sizeof(double), hipMemcpyHostToDevice));
   });
 }
 
@@ -820,6 +852,8 @@ fdu_status fdu_finalize(fdu_solver* s) {
     need(s != nullptr, "NULL solver");
     if (!s->have_edges || !s->have_vertices) throw Error(FDU_ERR_STATE, "upload edge and vertex stencils first");
     if (s->ng > 0 && s->gsrc.n != (size_t)s->ng) throw Error(FDU_ERR_STATE, "upload the ghosts first");
+    if (s->n_dirichlet > 0 && s->gstate.n != (size_t)(4 * s->ng))
+      throw Error(FDU_ERR_STATE, "upload the Dirichlet ghost states first (fdu_upload_ghost_states)");
     DeviceGuard dg(s->device);
     std::vector<double> c(2 * s->nv_real, 0.0);
     for (int64_t v = 0; v < s->nv_real; ++v)
@@ -1066,6 +1100,7 @@ fdu_status fdu_batch_set_states(fdu_batch* b, void* const* w, void* const* scrat
       I.sten = s->sten.p; I.geo = s->geo.p; I.vptr = s->vptr.p; I.vcol = s->vcol.p; I.wfg = s->wfg.p;
       I.eptr = s->eptr.p; I.ecol = s->ecol.p; I.we = s->we.p; I.cO = s->cO.p; I.hmin = s->hmin.p;
       I.gsrc = s->gsrc.p; I.grefl = reinterpret_cast<const signed char*>(s->grefl.p); I.flux = s->flux.p;
+      I.gstate = s->gstate.p;
       I.vblk = s->vblk.p; I.vb_uvp = s->vb_uvp.p; I.vb_uv = s->vb_uv.p; I.vb_uep = s->vb_uep.p; I.vb_ue = s->vb_ue.p;
       I.vb_lvcol = s->vb_lvcol.p; I.vb_lecol = s->vb_lecol.p;
       I.w = (double*)w[i];

@@ -55,6 +55,7 @@ _SIGS = {
     "fdu_upload_vertex_stencils": (I32, [VP, VP, VP, VP, VP, VP, VP, VP]),
     "fdu_upload_ghosts": (I32, [VP, I64, VP, VP]),
     "fdu_upload_prep": (I32, [VP, VP]),
+    "fdu_upload_ghost_states": (I32, [VP, I64, VP]),
     "fdu_finalize": (I32, [VP]),
     "fdu_sizes": (I32, [VP, P(I64), P(I64), P(I64), P(I64), P(I64)]),
     "fdu_fill_ghosts": (I32, [VP, VP, VP]),
@@ -139,7 +140,8 @@ class Prep:
               _ptr(edges, np.int32), tris.shape[0], _ptr(tris, np.int32),
               gs.ctypes.data_as(C.c_void_p) if gs.size else None,
               gr.ctypes.data_as(C.c_void_p) if gr.size else None,
-              int(mesh.periodic), float(mesh.box[0]), float(mesh.box[1]), deg, level, reorder, nthreads,
+              {True: 1, "y": 2}.get(mesh.periodic, 0), float(mesh.box[0]), float(mesh.box[1]), deg, level,
+              reorder, nthreads,
               int(bool(artificial)))
         self.handle = h
         v = PrepView()
@@ -184,7 +186,10 @@ class Solver:
     """Device-resident stencils and weights of one mesh; compute calls take
     torch tensors on the solver's device and run on torch's current stream."""
 
-    def __init__(self, prep: Prep | None = None, device: int = 0, precision: str = "f64", **params):
+    def __init__(self, prep: Prep | None = None, device: int = 0, precision: str = "f64", ghost_states=None,
+                 **params):
+        """ghost_states: [ng, 4] Dirichlet ghost states in the mesh's ghost order
+        (needed when the mesh has Dirichlet ghosts)."""
         self.device = device
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         self.prec = F64 if precision == "f64" else F32
@@ -195,8 +200,15 @@ class Solver:
         self.prep = prep
         if prep is not None:
             _call("fdu_upload_prep", h, prep.handle)
+            if ghost_states is not None:
+                self.set_ghost_states(ghost_states)
             _call("fdu_finalize", h)
             self._sizes()
+
+    def set_ghost_states(self, states):
+        """Dirichlet ghost states [ng, 4] (ghost order of the mesh = of the library)."""
+        g = np.ascontiguousarray(states, np.float64)
+        _call("fdu_upload_ghost_states", self.handle, g.shape[0], _ptr(g, np.float64))
 
     # -- uploads (library numbering)
     def upload(self, nv_total, nv_real, sten6, geo, vptr, vcol, wfg, eptr, ecol, we, hmin,

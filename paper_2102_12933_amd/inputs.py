@@ -19,7 +19,12 @@ Non-periodic meshes may carry a mirror ghost layer ``ghost_layers`` deep: ghost
 vertex positions and ghost triangles are the mirror images of the interior ones
 across the walls x=0, x=L, y=0, y=L.  Each ghost records its source vertex and
 which momentum components a reflecting wall negates (``ghost_refl`` bit 0: m_x,
-bit 1: m_y); filling ghost states from those is the solver's job.
+bit 1: m_y); filling ghost states from those is the solver's job.  Bit 2 marks a
+Dirichlet ghost: its state is a given boundary value (an array the caller
+passes beside the mesh), not a copy of its source.
+
+Channel meshes (``make_channel_mesh``) are periodic in y only (``periodic ==
+"y"``), with walls at x0 and x1 and mirror ghosts across those two walls.
 """
 from __future__ import annotations
 
@@ -36,7 +41,7 @@ class Mesh:
     nv_real: int            # vertices [0, nv_real) are real, the rest ghosts
     tri: np.ndarray         # [T, 3] int32 counter-clockwise triangles
     edges: np.ndarray       # [E, 2] int32, a < b, lexicographic order
-    periodic: bool
+    periodic: object        # True (both directions), False, or "y" (y only)
     box: tuple              # (Lx, Ly) domain size
     h: float                # nominal lattice spacing
     N: int
@@ -157,6 +162,68 @@ def make_mesh(N: int, L: float = 1.0, periodic: bool = True, jitter: float = 0.1
     return mesh
 
 
+def make_channel_mesh(Nx: int, Ny: int, x0: float, x1: float, y0: float, y1: float, jitter: float = 0.0,
+                      seed: int = 0, diag: str = "uniform", ghost_layers: int = 4, wall: str = "dirichlet") -> Mesh:
+    """Jittered triangulated lattice on [x0, x1] x [y0, y1), periodic in y.
+
+    x_i = x0 + i (x1 - x0) / (Nx - 1), i < Nx (walls at x0 and x1);
+    y_j = y0 + j (y1 - y0) / Ny, j < Ny (periodic).  Vertices off the two walls
+    are jittered (RNG: jitter [Nx*Ny, 2], then diagonal bits [Nx-1, Ny]).  A
+    mirror ghost layer ``ghost_layers`` deep lies across each wall; ``wall``:
+    "dirichlet" (ghost_refl bit 2: given boundary states), "reflect" (bit 0) or
+    "copy" (0).  Vertex id = i Ny + j.
+    """
+    if Nx < 3 or Ny < 3:
+        raise ValueError("Nx, Ny must be >= 3")
+    if diag not in ("random", "uniform") or wall not in ("dirichlet", "reflect", "copy"):
+        raise ValueError("diag: random|uniform, wall: dirichlet|reflect|copy")
+    rng = np.random.default_rng(seed)
+    hx, hy = (x1 - x0) / (Nx - 1), (y1 - y0) / Ny
+    jit = (rng.uniform(-jitter, jitter, size=(Nx * Ny, 2)) * np.array([hx, hy])) if jitter > 0 \
+        else np.zeros((Nx * Ny, 2))
+    bits = rng.integers(0, 2, size=(Nx - 1, Ny)).astype(np.int8) if diag == "random" \
+        else np.ones((Nx - 1, Ny), np.int8)
+    ii, jj = np.meshgrid(np.arange(Nx), np.arange(Ny), indexing="ij")
+    xy_real = np.stack([x0 + ii * hx, y0 + jj * hy], -1).reshape(-1, 2).astype(np.float64)
+    inner = ((ii > 0) & (ii < Nx - 1)).reshape(-1)
+    xy_real[inner] += jit[inner]
+    G = int(ghost_layers)
+    if G > Nx - 1:
+        raise ValueError("ghost_layers must be <= Nx-1")
+    M = Nx + 2 * G
+    lat = np.arange(M) - G                                     # extended x index in [-G, Nx-1+G]
+    src = np.where(lat < 0, -lat, np.where(lat > Nx - 1, 2 * (Nx - 1) - lat, lat))
+    outside = (lat < 0) | (lat > Nx - 1)
+    EI, EJ = np.meshgrid(np.arange(M), np.arange(Ny), indexing="ij")
+    li = lat[EI]
+    real = ~outside[EI]
+    ids = np.full((M, Ny), -1, np.int64)
+    ids[real] = li[real] * Ny + EJ[real]
+    ng = int((~real).sum())
+    ids[~real] = Nx * Ny + np.arange(ng)
+    gi, gj = li[~real], EJ[~real]
+    sid = src[EI][~real] * Ny + gj
+    gx = xy_real[sid, 0].copy()
+    gx = np.where(gi < 0, 2 * x0 - gx, 2 * x1 - gx)
+    xy = np.concatenate([xy_real, np.stack([gx, xy_real[sid, 1]], -1)], 0)
+    flag = {"dirichlet": 4, "reflect": 1, "copy": 0}[wall]
+    refl = np.full(ng, flag, np.int8)
+    qlat = np.arange(M - 1) - G
+    qsrc = np.where(qlat < 0, -qlat - 1, np.where(qlat > Nx - 2, 2 * Nx - 3 - qlat, qlat))
+    qout = ((qlat < 0) | (qlat > Nx - 2)).astype(np.int8)
+    QI, QJ = np.meshgrid(np.arange(M - 1), np.arange(Ny), indexing="ij")
+    QI, QJ = QI.ravel(), QJ.ravel()
+    qbit = bits[qsrc[QI], QJ] ^ qout[QI]
+    jp = (QJ + 1) % Ny
+    tri = _quad_tris(ids[QI, QJ], ids[QI + 1, QJ], ids[QI, jp], ids[QI + 1, jp], qbit)
+    mesh = Mesh(xy=xy, nv_real=Nx * Ny, tri=tri.astype(np.int32), edges=_edges_from_tris(tri),
+                periodic="y", box=(x1 - x0, y1 - y0), h=min(hx, hy), N=Nx,
+                ghost_src=sid.astype(np.int32), ghost_refl=refl)
+    mesh.meta = dict(Nx=Nx, Ny=Ny, x0=x0, x1=x1, y0=y0, y1=y1, jitter=jitter, seed=seed, diag=diag,
+                     ghost_layers=G, wall=wall)
+    return mesh
+
+
 # ----------------------------------------------------------------------------
 # Initial states (conservative variables w = [rho, rho u, rho v, rho E], Sec. 2.1)
 # ----------------------------------------------------------------------------
@@ -168,6 +235,16 @@ def primitive_to_conservative(rho, u, v, p, gamma: float = GAMMA) -> np.ndarray:
 
 def _wrap(d, L):
     return d - L * np.round(d / L)
+
+
+def _wrap_mesh(mesh, d):
+    """Displacements [..., 2] to their nearest periodic image on the mesh's box."""
+    d = np.array(d, dtype=np.float64, copy=True)
+    if mesh.periodic is True:
+        d[..., 0] = _wrap(d[..., 0], mesh.box[0])
+    if mesh.periodic is True or mesh.periodic == "y":
+        d[..., 1] = _wrap(d[..., 1], mesh.box[1])
+    return d
 
 
 def vortex_primitive(xy: np.ndarray, t=0.0, beta: float = 5.0, mach: float = 0.5,
@@ -235,6 +312,47 @@ def sod_state(mesh_or_xy, angle_deg: float = 30.0, center=(0.5, 0.5),
     return primitive_to_conservative(*prim, gamma=gamma)
 
 
+def normal_shock_states(mach: float = 1.2, gamma: float = GAMMA):
+    """Primitive (rho, u, v, p) on both sides of a stationary normal shock at x = 0
+    with the flow in -x: upstream (x > 0) rho = 1, p = 1/gamma (sound speed 1),
+    u = -mach; downstream from the Rankine-Hugoniot relations."""
+    M2 = mach * mach
+    r = (gamma + 1.0) * M2 / ((gamma - 1.0) * M2 + 2.0)          # density ratio
+    pr = 1.0 + 2.0 * gamma / (gamma + 1.0) * (M2 - 1.0)            # pressure ratio
+    up = (1.0, -mach, 0.0, 1.0 / gamma)
+    down = (r, -mach / r, 0.0, pr / gamma)
+    return up, down
+
+
+def shock_vortex_state(mesh, mach: float = 1.2, mv: float = 1.0, center=(4.0, 0.0), gamma: float = GAMMA):
+    """Shock-vortex interaction (Sec. 3.3): a stationary Mach-``mach`` normal shock
+    at x = 0 (flow in -x, upstream at x > 0) and an isentropic vortex of strength
+    ``mv`` centred upstream at ``center``:
+      rho = (1 - (gamma-1)/2 mv^2 exp(1 - r^2))^(1/(gamma-1)),  p = rho^gamma / gamma,
+      (du, dv) = mv exp((1 - r^2)/2) (-(y - yc), x - xc),
+    superposed on the upstream state (the exponent's factor reads (gamma-1)).
+    Returns (w [nv, 4], ghost_state [ng, 4]): the Dirichlet ghosts left of x = 0
+    hold the downstream state, those right of it the upstream state."""
+    up, down = normal_shock_states(mach, gamma)
+    xy = mesh.xy
+    dx, dy = xy[:, 0] - center[0], xy[:, 1] - center[1]
+    if mesh.periodic == "y":
+        dy = _wrap(dy, mesh.box[1])
+    r2 = dx * dx + dy * dy
+    rho_v = (1.0 - 0.5 * (gamma - 1.0) * mv * mv * np.exp(1.0 - r2)) ** (1.0 / (gamma - 1.0))
+    amp = mv * np.exp(0.5 * (1.0 - r2))
+    upstream = xy[:, 0] > 0.0
+    rho = np.where(upstream, up[0] * rho_v, down[0])
+    u = np.where(upstream, up[1] - amp * dy, down[1])
+    v = np.where(upstream, up[2] + amp * dx, down[2])
+    p = np.where(upstream, rho_v ** gamma / gamma, down[3])
+    w = primitive_to_conservative(rho, u, v, p, gamma=gamma)
+    gx = xy[mesh.nv_real:, 0]
+    gs = np.where((gx > 0.0)[:, None], primitive_to_conservative(*[np.array(q) for q in up], gamma=gamma)[None, :],
+                  primitive_to_conservative(*[np.array(q) for q in down], gamma=gamma)[None, :])
+    return w, np.ascontiguousarray(gs)
+
+
 def batch_specs(n: int = 64, n_min: int = 65, n_max: int = 513, seed: int = 42,
                 beta_range=(2.0, 6.0), mach_range=(0.3, 0.8), mesh_seed0: int = 1000):
     """Instance table of the batched vortex workload: N_i ~ U{n_min..n_max},
@@ -256,9 +374,7 @@ def vertex_areas(mesh) -> np.ndarray:
     d1 = mesh.xy[t[:, 1]] - p0
     d2 = mesh.xy[t[:, 2]] - p0
     if mesh.periodic:
-        L = np.asarray(mesh.box)
-        d1 = d1 - L * np.round(d1 / L)
-        d2 = d2 - L * np.round(d2 / L)
+        d1, d2 = _wrap_mesh(mesh, d1), _wrap_mesh(mesh, d2)
     area = 0.5 * np.abs(d1[:, 0] * d2[:, 1] - d1[:, 1] * d2[:, 0])
     A = np.zeros(mesh.nv)
     for k in range(3):

@@ -1,0 +1,169 @@
+"""Dirichlet boundaries and the shock-vortex interaction of Sec. 3.3 on the GPU:
+parity with the oracle on small channels (residual, RK stage, ghost fill,
+adjoint, batch), and the full problem to t = 16."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import euler
+from oracle.solver import Oracle
+from paper_2102_12933_amd.inputs import GAMMA, make_channel_mesh, normal_shock_states, shock_vortex_state
+from tests._helpers import rel_err_per_component
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _fdu():
+    from paper_2102_12933_amd import fdu
+    return fdu
+
+
+def channel(seed=1, center=(2.5, 0.0), mv=1.0, deg=5, reorder=2, **params):
+    fdu = _fdu()
+    m = make_channel_mesh(24, 20, -6.0, 6.0, -5.0, 5.0, jitter=0.1, seed=seed, diag="random")
+    w0, gs = shock_vortex_state(m, center=center, mv=mv)
+    prep = fdu.Prep(m, deg=deg, reorder=reorder)
+    perm = prep.arrays()["perm"]
+    s = fdu.Solver(prep, device=0, ghost_states=gs, **params)
+    return m, w0, gs, perm, s
+
+
+@pytest.mark.parametrize("edge,vertex", [(0, 0), (1, 3), (1, 10)])
+def test_dirichlet_channel_residual_and_stage(edge, vertex):
+    m, w0, gs, perm, s = channel()
+    s.set_variants(edge, vertex)
+    o = Oracle(m, deg=5, ghost_state=gs)
+    w = torch.from_numpy(np.ascontiguousarray(w0[perm])).cuda()
+    R = s.residual(w).cpu().numpy()
+    Ro = o.residual(torch.from_numpy(w0)).numpy()[perm[:m.nv_real]]
+    assert rel_err_per_component(R, Ro).max() <= TOL
+    # ghost rows after the fill: the given Dirichlet states, in ghost order
+    wf = w.cpu().numpy()
+    np.testing.assert_array_equal(wf[m.nv_real:], gs)
+    dt = torch.full((1,), 0.01, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(w)
+    s.rk_stage(1, w, w.clone(), out, dt)
+    ref = o.rk3_stage(1, torch.from_numpy(w0), torch.from_numpy(w0), 0.01).numpy()[perm]
+    assert rel_err_per_component(out.cpu().numpy()[:m.nv_real], ref[:m.nv_real]).max() <= 1e-14
+
+
+def test_dirichlet_ghost_states_required_and_updatable():
+    fdu = _fdu()
+    m = make_channel_mesh(10, 8, -2.0, 2.0, -1.0, 1.0)
+    w0, gs = shock_vortex_state(m, center=(1.0, 0.0))
+    prep = fdu.Prep(m, deg=3, reorder=1)
+    with pytest.raises(fdu.FduError, match="STATE"):
+        fdu.Solver(prep, device=0)
+    s = fdu.Solver(prep, device=0, ghost_states=gs)
+    w = torch.from_numpy(np.ascontiguousarray(w0[prep.arrays()["perm"]])).cuda()
+    s.fill_ghosts(w)
+    gs2 = gs.copy()
+    gs2[:, 0] *= 1.5
+    s.set_ghost_states(gs2)
+    s.fill_ghosts(w)
+    np.testing.assert_array_equal(w.cpu().numpy()[m.nv_real:], gs2)
+    bad = gs.copy()
+    bad[0, 0] = -1.0
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        s.set_ghost_states(bad)
+
+
+def test_dirichlet_channel_residual_vjp():
+    m, w0, gs, perm, s = channel(weno_eps=1e-6)
+    s.enable_adjoint()
+    o = Oracle(m, deg=5, ghost_state=gs, weno_eps=1e-6)
+    rng = np.random.default_rng(3)
+    Rbar = rng.normal(size=(m.nv_real, 4))
+    g = s.residual_vjp(torch.from_numpy(np.ascontiguousarray(w0[perm])).cuda(),
+                       torch.from_numpy(np.ascontiguousarray(Rbar[perm[:m.nv_real]])).cuda()).cpu().numpy()
+    go = o.residual_vjp(torch.from_numpy(w0), torch.from_numpy(Rbar)).numpy()[perm]
+    nr = m.nv_real
+    assert rel_err_per_component(g[:nr], go[:nr]).max() <= TOL
+    assert np.abs(g[nr:]).max() == 0.0
+
+
+@pytest.mark.parametrize("schedule,vmode", [(0, 2), (1, 3), (2, 0)])
+def test_dirichlet_batch_equals_plain(schedule, vmode):
+    fdu = _fdu()
+    inst = [channel(seed=k, center=(2.0 + k, 0.5 * k), mv=0.6 + 0.2 * k) for k in range(3)]
+    ref = []
+    for m, w0, gs, perm, s in inst:
+        s.set_variants(1, {0: 0, 2: 3, 3: 10}[vmode])
+        w = torch.from_numpy(np.ascontiguousarray(w0[perm])).cuda()
+        scr = torch.empty(2 * m.nv, 4, dtype=torch.float64, device="cuda")
+        dt = torch.empty(1, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            s.rk_step(w, scr, dt, cfl=0.4)
+        ref.append(w.cpu())
+    b = fdu.Batch([s for *_, s in inst])
+    b.set_schedule(schedule, 4, 8, vmode)
+    ws = [torch.from_numpy(np.ascontiguousarray(w0[perm])).cuda() for _, w0, _, perm, _ in inst]
+    scr = [torch.empty(2 * m.nv, 4, dtype=torch.float64, device="cuda") for m, *_ in inst]
+    b.set_states(ws, scr)
+    for _ in range(3):
+        b.step(0.4)
+    err, _ = b.status()
+    assert err == 0
+    for w, r in zip(ws, ref):
+        assert torch.equal(w.cpu(), r)
+
+
+@pytest.mark.slow
+def test_shock_vortex_to_t16():
+    """Sec. 3.3: [-65, 15] x [-40, 40], Mach-1.2 stationary shock at x = 0,
+    vortex (M_v = 1) at (4, 0), Dirichlet at x walls, periodic in y, spacing
+    0.08 (the paper's finest edge length, here everywhere: 1001 x 1000
+    vertices, regular diagonalized mesh), SSP-RK3 at CFL 0.5 to t = 16."""
+    fdu = _fdu()
+    m = make_channel_mesh(1001, 1000, -65.0, 15.0, -40.0, 40.0, jitter=0.0, diag="uniform", ghost_layers=4)
+    w0, gs = shock_vortex_state(m)
+    t0 = time.perf_counter()
+    prep = fdu.Prep(m, deg=5, reorder=2)
+    perm = prep.arrays()["perm"]
+    s = fdu.Solver(prep, device=0, ghost_states=gs)
+    print(f"prep {time.perf_counter() - t0:.1f} s", flush=True)
+    w = torch.from_numpy(np.ascontiguousarray(w0[perm])).cuda()
+    scr = torch.empty(2 * m.nv, 4, dtype=torch.float64, device="cuda")
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    t, steps = 0.0, 0
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    while t < 16.0 - 1e-12:
+        s.cfl_dt(w, 0.5, dt)
+        d = float(dt.item())
+        if t + d > 16.0:
+            d = 16.0 - t
+            dt.fill_(d)
+        s.rk_step(w, scr, dt)
+        t += d
+        steps += 1
+        if steps % 200 == 0:
+            assert bool(torch.isfinite(w).all()), (steps, t)
+            print(f"step {steps} t {t:.3f}", flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    out = np.empty((m.nv, 4))
+    out[perm] = w.cpu().numpy()
+    rho, u, v, p = [x.numpy() for x in euler.primitives(torch.from_numpy(out[:m.nv_real]), GAMMA)]
+    print(f"{steps} steps to t = 16 in {el:.2f} s ({m.nv_real * 3 * steps / el:.3e} vertex-stage/s); "
+          f"rho [{rho.min():.4f}, {rho.max():.4f}], p [{p.min():.4f}, {p.max():.4f}]", flush=True)
+    assert np.isfinite(out).all() and rho.min() > 0 and p.min() > 0
+    # away from the vortex path the shock stays at x = 0: density midway between the two states there
+    up, down = normal_shock_states(1.2)
+    x, y = m.xy[:m.nv_real, 0], m.xy[:m.nv_real, 1]
+    band = np.abs(np.abs(y) - 37.5) < 2.5
+    mid = 0.5 * (up[0] + down[0])
+    for yy in np.unique(np.round(y[band], 6))[::25]:
+        row = np.abs(y - yy) < 1e-9
+        xs, rs = x[row], rho[row]
+        o = np.argsort(xs)
+        xs, rs = xs[o], rs[o]
+        k = np.nonzero((rs[:-1] - mid) * (rs[1:] - mid) <= 0)[0]
+        assert len(k) >= 1
+        assert np.min(np.abs(xs[k])) < 0.5, (yy, xs[k])
+    # the vortex has passed through the shock and is downstream (x < 0)
+    core = np.argmin(p)
+    assert x[core] < -2.0, (x[core], y[core])
