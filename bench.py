@@ -259,6 +259,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--adjoint-N", type=int, default=257)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 512 MiB buffer 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -321,6 +322,24 @@ def main():
         raise RuntimeError("non-physical state after a step")
     log(f"timed {args.steps} steps: {el * 1e3:.2f} ms; live kernel means (ms) {kt}, launches {kcount}")
 
+    # the same steps captured in one HIP graph (launch gaps removed); reported beside the headline
+    graph = None
+    if not args.no_graph:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(args.steps):
+                step()
+        g.replay()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        elg = time.perf_counter() - tg
+        graph = dict(ms_per_step=round(elg / args.steps * 1e3, 4),
+                     vertex_stage_per_s=A["nv_real"] * 3 * args.steps / elg)
+        log(f"graph replay of {args.steps} steps: {elg * 1e3:.2f} ms")
+        del g
+
     blocks = solver.vertex_block_info() if tune["vertex"] in (10, 11) else None
     nb = kernel_bytes(A, blocks=blocks)
     kern = {}
@@ -359,6 +378,7 @@ def main():
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in d.items()}
                     for k, d in kern.items()} | {"ghost_ms": round(kt["ghost"], 5), "cfl_ms": round(kt["cfl"], 5)},
         "vertex_blocks": blocks,
+        "graph_replay": graph,
         "autotune": {"edge_variant": tune["edge"], "vertex_variant": tune["vertex"],
                      "edge_ms": [round(t, 5) for t in tune["edge_ms"]],
                      "vertex_ms": [round(t, 5) for t in tune["vertex_ms"]]},

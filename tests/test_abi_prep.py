@@ -35,7 +35,8 @@ CASES = [(33, True, 0, 3, 1, False), (33, True, 0, 5, 1, False), (18, False, 4, 
          (18, False, 4, 5, 1, False),
          (65, False, 4, 5, 1, False),   # 65^2 seed 3 and 0: mirror-ghost corners with rank-deficient systems
          (33, True, 0, 5, 2, False), (18, False, 4, 5, 2, False),    # Hilbert order
-         (33, True, 0, 3, 1, True), (18, False, 4, 3, 2, True)]      # artificial edges
+         (33, True, 0, 3, 1, True), (18, False, 4, 3, 2, True),      # artificial edges
+         (20, True, 0, 4, 2, False), (16, False, 4, 4, 2, False), (24, True, 0, 6, 2, False)]   # degrees 4, 6
 
 
 @pytest.mark.parametrize("N,periodic,ghosts,deg,reorder,artificial", CASES)
@@ -125,3 +126,13 @@ def test_prep_rejects_bad_input():
         fdu.Prep(m2, deg=3)
     with pytest.raises(fdu.FduError, match="INVALID_ARG"):
         fdu.Prep(m, deg=9)
+
+
+def test_degree_six_needs_more_than_a_mirrored_wall_stencil():
+    """Next to a mirrored wall a two-level stencil has too few independent
+    conditions for degree 6 (54 unknowns); prep and oracle both refuse it."""
+    m = make_mesh(16, L=1.0, periodic=False, seed=3, ghost_layers=4)
+    with pytest.raises(fdu.FduError, match="NUMERIC"):
+        fdu.Prep(m, deg=6)
+    with pytest.raises(ValueError, match="not determined"):
+        Oracle(m, deg=6)

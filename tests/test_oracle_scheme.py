@@ -106,7 +106,7 @@ def test_ls_weights_minimum_norm_on_two_level():
     np.testing.assert_allclose(Q @ (Q.T @ rho), rho, atol=1e-10 * np.abs(rho).max())
 
 
-@pytest.mark.parametrize("deg,artificial", [(3, False), (5, False), (3, True)])
+@pytest.mark.parametrize("deg,artificial", [(3, False), (4, False), (5, False), (6, False), (3, True)])
 def test_divergence_exact_for_polynomials(deg, artificial):
     m = make_mesh(16, L=1.0, periodic=False, seed=5, ghost_layers=4)
     verts = np.arange(0, m.nv_real, 3)
