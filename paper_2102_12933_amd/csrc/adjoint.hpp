@@ -435,21 +435,30 @@ FDU_HD void edge_vjp_one(Load&& load, const double g[6], const double ob[4], con
   }
 }
 
-// rbar_k = -sum_{O uses k} we_Ok Rbar_O (transposed edge CSR)
-template <class T, class TW>
+// rbar_k = -sum_{O uses k} we_Ok Rbar_O (transposed edge CSR); LPV lanes per
+// edge take strided shares of its ~44 entries and a butterfly sums them.
+template <class T, class TW, int LPV>
 __global__ void __launch_bounds__(256) k_edge_cot(const int* __restrict__ tptr, const int* __restrict__ trow,
                                                   const TW* __restrict__ tw, const T* __restrict__ Rbar,
                                                   double* __restrict__ rbar, int ne) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= ne) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = t / LPV, lane = t % LPV;
+  const bool active = k < ne;
   double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int p = tptr[k]; p < tptr[k + 1]; ++p) {
-    double q[4];
-    load4(Rbar, trow[p], q);
-    const double c = (double)tw[p];
+  if (active) {
+    for (int p = tptr[k] + lane; p < tptr[k + 1]; p += LPV) {
+      double q[4];
+      load4(Rbar, trow[p], q);
+      const double c = (double)tw[p];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] -= c * q[i];
+      for (int i = 0; i < 4; ++i) a[i] -= c * q[i];
+    }
   }
+#pragma unroll
+  for (int m = LPV / 2; m >= 1; m >>= 1)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] += __shfl_xor(a[i], m, LPV);
+  if (!active || lane != 0) return;
   double2* o = reinterpret_cast<double2*>(rbar + 4 * (size_t)k);
   o[0] = make_double2(a[0], a[1]);
   o[1] = make_double2(a[2], a[3]);
@@ -482,26 +491,44 @@ __global__ void __launch_bounds__(256, 2) k_edge_vjp(const T* __restrict__ w, co
 
 // Per vertex (real and ghost): flux-cotangent gathers over the transposed
 // vertex CSR, the flux Jacobian transposes, and the edge slots that read it.
-template <class T, class TW>
+// LPV lanes per vertex share both gather loops; a butterfly sums them.
+template <class T, class TW, int LPV>
 __global__ void __launch_bounds__(256) k_vertex_vjp(const T* __restrict__ w, const T* __restrict__ Rbar,
                                                     const int* __restrict__ tptr, const int* __restrict__ trow,
                                                     const TW* __restrict__ twfg, const double* __restrict__ sfg,
                                                     const int* __restrict__ sptr, const int* __restrict__ scol,
                                                     const double* __restrict__ slots, int nreal, int nv,
                                                     double gm1, double* __restrict__ tmp) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nv) return;
-  double fb[4] = {0.0, 0.0, 0.0, 0.0}, gb[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int p = tptr[v]; p < tptr[v + 1]; ++p) {
-    double q[4];
-    load4(Rbar, trow[p], q);
-    const double a = (double)twfg[2 * (size_t)p], b = (double)twfg[2 * (size_t)p + 1];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = t / LPV, lane = t % LPV;
+  const bool active = v < nv;
+  double fb[4] = {0.0, 0.0, 0.0, 0.0}, gb[4] = {0.0, 0.0, 0.0, 0.0}, sl[4] = {0.0, 0.0, 0.0, 0.0};
+  if (active) {
+    for (int p = tptr[v] + lane; p < tptr[v + 1]; p += LPV) {
+      double q[4];
+      load4(Rbar, trow[p], q);
+      const double a = (double)twfg[2 * (size_t)p], b = (double)twfg[2 * (size_t)p + 1];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      fb[i] -= a * q[i];
-      gb[i] -= b * q[i];
+      for (int i = 0; i < 4; ++i) {
+        fb[i] -= a * q[i];
+        gb[i] -= b * q[i];
+      }
+    }
+    for (int p = sptr[v] + lane; p < sptr[v + 1]; p += LPV) {
+      const double2* sp = reinterpret_cast<const double2*>(slots + 4 * (size_t)scol[p]);
+      const double2 x = sp[0], y = sp[1];
+      sl[0] += x.x; sl[1] += x.y; sl[2] += y.x; sl[3] += y.y;
     }
   }
+#pragma unroll
+  for (int m = LPV / 2; m >= 1; m >>= 1)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      fb[i] += __shfl_xor(fb[i], m, LPV);
+      gb[i] += __shfl_xor(gb[i], m, LPV);
+      sl[i] += __shfl_xor(sl[i], m, LPV);
+    }
+  if (!active || lane != 0) return;
   if (v < nreal) {
     double q[4];
     load4(Rbar, v, q);
@@ -529,16 +556,11 @@ __global__ void __launch_bounds__(256) k_vertex_vjp(const T* __restrict__ w, con
     const Dual<4> g[4] = {q[2], q[2] * u, q[2] * vv + p, (q[3] + p) * vv};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      double t = 0.0;
+      double t2 = 0.0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) t += fb[i] * f[i].d[k] + gb[i] * g[i].d[k];
-      wb[k] = t;
+      for (int i = 0; i < 4; ++i) t2 += fb[i] * f[i].d[k] + gb[i] * g[i].d[k];
+      wb[k] = t2 + sl[k];
     }
-  }
-  for (int p = sptr[v]; p < sptr[v + 1]; ++p) {
-    const double2* sp = reinterpret_cast<const double2*>(slots + 4 * (size_t)scol[p]);
-    const double2 a = sp[0], b = sp[1];
-    wb[0] += a.x; wb[1] += a.y; wb[2] += b.x; wb[3] += b.y;
   }
   double2* o = reinterpret_cast<double2*>(tmp + 4 * (size_t)v);
   o[0] = make_double2(wb[0], wb[1]);

@@ -89,8 +89,8 @@ struct fdu_solver {
     for (auto& v : timer_ev)
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
   }
-  int edge_variant = 0;    // 0: k_edge_flux, 1: k_edge_flux_lean
-  int vertex_variant = 0;  // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair, 10-11: k_vertex_lds
+  int edge_variant = 1;    // 0: k_edge_flux, 1: k_edge_flux_lean
+  int vertex_variant = 3;  // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair, 10-11: k_vertex_lds
 };
 
 namespace {
@@ -472,22 +472,23 @@ void residual_vjp_t(fdu_solver* s, T* w, const T* Rbar, T* out, double alpha, co
   const Scheme S = scheme_of(s);
   const int ne = (int)s->ne_flux, nv = (int)s->nv_total, nr = (int)s->nv_real;
   fill_ghosts_t<T>(s, w, st);
+  constexpr int kLanes = 8;   // lanes per edge / vertex in the transposed gathers
   if (s->prec == FDU_F64) {
-    hipLaunchKernelGGL((k_edge_cot<T, double>), dim3(nblocks(ne)), dim3(256), 0, st, s->te_ptr.p, s->te_row.p,
-                       s->te_w.p, Rbar, s->rbar.p, ne);
+    hipLaunchKernelGGL((k_edge_cot<T, double, kLanes>), dim3(nblocks((int64_t)ne * kLanes)), dim3(256), 0, st,
+                       s->te_ptr.p, s->te_row.p, s->te_w.p, Rbar, s->rbar.p, ne);
     hipLaunchKernelGGL((k_edge_vjp<T, double>), dim3(nblocks(ne)), dim3(256), 0, st, w, s->sten.p, s->geo.p,
                        s->rbar.p, s->slots.p, ne, S);
-    hipLaunchKernelGGL((k_vertex_vjp<T, double>), dim3(nblocks(nv)), dim3(256), 0, st, w, Rbar, s->tv_ptr.p,
-                       s->tv_row.p, s->tv_wfg.p, s->sfg.p, s->ts_ptr.p, s->ts_col.p, s->slots.p, nr, nv, S.gm1,
-                       s->vtmp.p);
+    hipLaunchKernelGGL((k_vertex_vjp<T, double, kLanes>), dim3(nblocks((int64_t)nv * kLanes)), dim3(256), 0, st, w,
+                       Rbar, s->tv_ptr.p, s->tv_row.p, s->tv_wfg.p, s->sfg.p, s->ts_ptr.p, s->ts_col.p, s->slots.p,
+                       nr, nv, S.gm1, s->vtmp.p);
   } else {
-    hipLaunchKernelGGL((k_edge_cot<T, float>), dim3(nblocks(ne)), dim3(256), 0, st, s->te_ptr.p, s->te_row.p,
-                       s->te_w32.p, Rbar, s->rbar.p, ne);
+    hipLaunchKernelGGL((k_edge_cot<T, float, kLanes>), dim3(nblocks((int64_t)ne * kLanes)), dim3(256), 0, st,
+                       s->te_ptr.p, s->te_row.p, s->te_w32.p, Rbar, s->rbar.p, ne);
     hipLaunchKernelGGL((k_edge_vjp<T, float>), dim3(nblocks(ne)), dim3(256), 0, st, w, s->sten.p, s->geo32.p,
                        s->rbar.p, s->slots.p, ne, S);
-    hipLaunchKernelGGL((k_vertex_vjp<T, float>), dim3(nblocks(nv)), dim3(256), 0, st, w, Rbar, s->tv_ptr.p,
-                       s->tv_row.p, s->tv_wfg32.p, s->sfg.p, s->ts_ptr.p, s->ts_col.p, s->slots.p, nr, nv, S.gm1,
-                       s->vtmp.p);
+    hipLaunchKernelGGL((k_vertex_vjp<T, float, kLanes>), dim3(nblocks((int64_t)nv * kLanes)), dim3(256), 0, st, w,
+                       Rbar, s->tv_ptr.p, s->tv_row.p, s->tv_wfg32.p, s->sfg.p, s->ts_ptr.p, s->ts_col.p, s->slots.p,
+                       nr, nv, S.gm1, s->vtmp.p);
   }
   launch_check();
   hipLaunchKernelGGL(k_ghost_vjp<T>, dim3(nblocks(nv)), dim3(256), 0, st, s->vtmp.p, s->tg_ptr.p, s->tg_col.p,
