@@ -187,6 +187,42 @@ def bench_batched(n_inst, steps, cfl, edge_variant, vertex_variant, log):
                 schedules=res, autotune_ms={",".join(map(str, k)): round(v, 4) for k, v in tune_ms.items()})
 
 
+def bench_fp32(prep, A, w0_f64, steps, cfl, log):
+    """The headline workload in FP32 storage (state, geometry and weights in
+    FP32, arithmetic and edge fluxes in FP64): the same non-chained steps."""
+    import torch
+    from paper_2102_12933_amd import fdu
+
+    s = fdu.Solver(prep, device=0, precision="f32")
+    w0 = w0_f64.float()
+    w1, w2, w3 = (torch.empty_like(w0) for _ in range(3))
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    s.fill_ghosts(w0)
+    tune = s.autotune(w0, reps=10)
+
+    def step():
+        s.cfl_dt(w0, cfl, dt)
+        s.rk_stage(0, w0, w0, w1, dt)
+        s.rk_stage(1, w0, w1, w2, dt)
+        s.rk_stage(2, w0, w2, w3, dt)
+
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    s.kernel_timer_start(capacity=3 * steps + 8)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt, _ = s.kernel_timer_stop()
+    ok = bool(torch.isfinite(w3[:A["nv_real"]]).all())
+    log(f"fp32 storage: {el / steps * 1e3:.3f} ms/step, vertex {kt['vertex'] * 1e3:.1f} us, edge {kt['edge'] * 1e3:.1f} us")
+    return dict(ms_per_step=round(el / steps * 1e3, 4), vertex_stage_per_s=A["nv_real"] * 3 * steps / el,
+                vertex_ms=round(kt["vertex"], 5), edge_ms=round(kt["edge"], 5), finite=ok,
+                variants=[tune["edge"], tune["vertex"]])
+
+
 def bench_adjoint(N, nsteps, ckpt, log):
     """Unrolled-gradient workload: vortex on an N^2 jittered periodic mesh, nsteps
     SSP-RK3 steps at the t = 0 CFL-0.5 time step, checkpoints every ckpt steps,
@@ -260,6 +296,7 @@ def main():
     ap.add_argument("--adjoint-N", type=int, default=257)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 512 MiB buffer 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -399,6 +436,8 @@ def main():
                      "edge_ms": [round(t, 5) for t in tune["edge_ms"]],
                      "vertex_ms": [round(t, 5) for t in tune["vertex_ms"]]},
     }
+    if not args.no_fp32:
+        out["fp32_storage"] = bench_fp32(prep, A, w0, min(args.steps, 100), args.cfl, log)
     if not args.no_batch:
         out["batched"] = bench_batched(args.batch_instances, args.batch_steps, 0.2, tune["edge"], tune["vertex"], log)
     if not args.no_adjoint:
