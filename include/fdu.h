@@ -338,6 +338,14 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
  * variant on the given state with fdu_kernel_times (reps launches each),
  * writes the mean times (ms) to times_ms[0 .. n_edge + n_vertex - 1] and keeps
  * the fastest of each; synchronous; w and scratch as for fdu_kernel_times. */
+/* fdu_check_state: failure detection for long runs.  Counts the real rows of
+ * w (device state, the solver's precision) that are not finite or not
+ * physical (rho <= 0 or p <= 0), writes the count to *n_bad and the smallest
+ * such row (library numbering) to *first_bad (-1 when none).  Runs on stream
+ * and waits for it (not for use inside graph capture).  FDU_ERR_STATE before
+ * fdu_finalize. */
+fdu_status fdu_check_state(fdu_solver* s, const void* w, int64_t* n_bad, int64_t* first_bad, void* stream);
+
 /* fdu_vertex_block_info: the vertex blocks built at fdu_finalize for the
  * LDS-staged vertex variants: their number, the total length of their row
  * lists (state rows + flux rows, with repeats across blocks) and the largest

@@ -1143,6 +1143,28 @@ __global__ void __launch_bounds__(256, WPE) k_vertex_lds(const T* __restrict__ w
                                            lvcol, wfg, eptr, lecol, we, cO, r, gm1, mode, R, wn, out, a, b, dt_dev);
 }
 
+// State check: counts real rows that are not finite or not physical
+// (rho <= 0 or p <= 0) and keeps the smallest such row index.
+template <class T>
+__global__ void __launch_bounds__(256) k_check_state(const T* __restrict__ w, int nreal, double gm1,
+                                                     unsigned long long* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nreal) return;
+  double q[4];
+  load4(w, v, q);
+  const bool finite = isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3]);
+  if (finite && physical(q, gm1)) return;
+  atomicAdd(&out[0], 1ull);
+  atomicMin(&out[1], (unsigned long long)v);
+}
+
+__global__ void k_check_reset(unsigned long long* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = 0ull;
+    out[1] = ~0ull;
+  }
+}
+
 // CFL time step: per-block minima of hmin_v / (|u_v| + c_v), then one block
 // reduces them and writes cfl * min.
 template <class T>

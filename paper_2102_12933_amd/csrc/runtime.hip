@@ -73,6 +73,7 @@ struct fdu_solver {
   DevBuf<double> gstate;     // [ng][4] Dirichlet ghost states (rows of other ghosts unused)
   int64_t n_dirichlet = 0;
   DevBuf<double> geo, wfg, we, cO, hmin, flux, part;
+  DevBuf<unsigned long long> chk;   // fdu_check_state: count, first bad row
   DevBuf<float> geo32, wfg32, we32;
   int cfl_blocks = 0;
   // vertex blocks with their stencil halos (LDS-staged vertex variants)
@@ -886,6 +887,29 @@ fdu_status fdu_sizes(const fdu_solver* s, int64_t* nv_total, int64_t* nv_real, i
     if (ne_flux) *ne_flux = s->ne_flux;
     if (nnz_v) *nnz_v = s->nnz_v;
     if (nnz_e) *nnz_e = s->nnz_e;
+  });
+}
+
+fdu_status fdu_check_state(fdu_solver* s, const void* w, int64_t* n_bad, int64_t* first_bad, void* stream) {
+  return guard([&] {
+    ready(s);
+    need(w && n_bad && first_bad, "NULL argument");
+    DeviceGuard dg(s->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (s->chk.n != 2) s->chk.alloc(2);
+    hipLaunchKernelGGL(k_check_reset, dim3(1), dim3(64), 0, st, s->chk.p);
+    if (s->prec == FDU_F64)
+      hipLaunchKernelGGL(k_check_state<double>, dim3(nblocks(s->nv_real)), dim3(256), 0, st, (const double*)w,
+                         (int)s->nv_real, s->params.gamma - 1.0, s->chk.p);
+    else
+      hipLaunchKernelGGL(k_check_state<float>, dim3(nblocks(s->nv_real)), dim3(256), 0, st, (const float*)w,
+                         (int)s->nv_real, s->params.gamma - 1.0, s->chk.p);
+    launch_check();
+    unsigned long long h[2];
+    FDU_HIP(hipMemcpyAsync(h, s->chk.p, sizeof(h), hipMemcpyDeviceToHost, st));
+    FDU_HIP(hipStreamSynchronize(st));
+    *n_bad = (int64_t)h[0];
+    *first_bad = h[0] ? (int64_t)h[1] : -1;
   });
 }
 

@@ -67,6 +67,7 @@ _SIGS = {
     "fdu_kernel_times": (I32, [VP, VP, VP, I32, VP, VP]),
     "fdu_kernel_timer_start": (I32, [VP, I32]),
     "fdu_vertex_block_info": (I32, [VP, P(I32), P(I64), P(I32)]),
+    "fdu_check_state": (I32, [VP, VP, P(I64), P(I64), VP]),
     "fdu_kernel_timer_stop": (I32, [VP, VP, VP]),
     "fdu_enable_adjoint": (I32, [VP]),
     "fdu_set_variants": (I32, [VP, I32, I32]),
@@ -333,6 +334,12 @@ class Solver:
         _call("fdu_kernel_times", self.handle, self._state(w), C.c_void_p(scratch.data_ptr()), int(reps), out,
               _stream())
         return dict(ghost=out[0], edge=out[1], vertex=out[2], cfl=out[3])
+
+    def check_state(self, w):
+        """(number of non-finite or non-physical real rows, first such row or -1)."""
+        n, first = C.c_int64(), C.c_int64()
+        _call("fdu_check_state", self.handle, self._state(w), C.byref(n), C.byref(first), _stream())
+        return n.value, first.value
 
     def vertex_block_info(self):
         """Vertex blocks of the LDS-staged variants: count, total and largest row list."""

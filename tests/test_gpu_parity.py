@@ -353,3 +353,38 @@ def test_free_stream_preserved_on_the_gpu(edge, vertex):
         w = torch.tensor(q, dtype=torch.float64).repeat(m.nv, 1).cuda()
         R = s.residual(w)
         assert float(R.abs().max()) < 1e-12 / m.h, float(R.abs().max())
+
+
+def test_check_state_flags_bad_rows():
+    """Failure detection: a physical state has no bad rows; rows made
+    non-finite, with negative density or with negative pressure are counted and
+    the first one reported (library numbering)."""
+    c = Case(16, True, 0, 3, "vortex")
+    w = c.w_dev()
+    assert c.s.check_state(w) == (0, -1)
+    w[7, 0] = float("nan")
+    w[3, 0] = -1.0
+    w[11, 3] = 0.0        # E = 0 with nonzero momentum: p < 0
+    n, first = c.s.check_state(w)
+    assert n == 3 and first == 3
+
+
+def test_checkpoint_resume_is_bitwise(tmp_path):
+    """Ten steps in one go equal five steps, a checkpoint, a reload and five more."""
+    from paper_2102_12933_amd.checkpoint import load_state, save_state
+    c = Case(20, True, 0, 5, "vortex")
+    scr = torch.empty(2 * c.m.nv, 4, dtype=torch.float64, device="cuda")
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    a = c.w_dev()
+    for _ in range(10):
+        c.s.rk_step(a, scr, dt, cfl=0.5)
+    b = c.w_dev()
+    for _ in range(5):
+        c.s.rk_step(b, scr, dt, cfl=0.5)
+    p = str(tmp_path / "ck.npz")
+    save_state(p, c.prep, b, step=5)
+    b2, step, _ = load_state(p, c.prep)
+    assert step == 5
+    for _ in range(5):
+        c.s.rk_step(b2, scr, dt, cfl=0.5)
+    assert torch.equal(a, b2)
