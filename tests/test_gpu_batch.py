@@ -116,3 +116,38 @@ def test_batch_lds_mode_rejects_persistent_schedule():
     b = fdu.Batch([s for s, _ in inst])
     with pytest.raises(fdu.FduError, match="UNSUPPORTED"):
         b.set_schedule(0, 4, 8, 3)
+
+
+@pytest.mark.slow
+def test_full_batch_workload_sampled():
+    """The batched workload at full size (64 instances, 7.0 M vertices, Hilbert
+    order, the per-phase schedule with LDS vertex blocks and the fused
+    persistent schedule): three steps at CFL 0.2 equal the plain path bit for
+    bit on a sample of instances, and no dependency wait times out."""
+    fdu = _fdu()
+    specs = batch_specs(n=64)
+    inst = []
+    for sp in specs:
+        m = make_mesh(sp["N"], L=10.0, periodic=True, seed=sp["seed"])
+        prep = fdu.Prep(m, deg=5, reorder=2)
+        perm = prep.arrays()["perm"]
+        s = fdu.Solver(prep, device=0)
+        w0 = torch.from_numpy(np.ascontiguousarray(vortex_state(m, beta=sp["beta"], mach=sp["mach"])[perm])).cuda()
+        inst.append((s, w0))
+    sample = [0, 17, 40, 63]
+    for schedule, vmode, plain_vertex in ((1, 3, 10), (0, 2, 3)):
+        for s, _ in inst:
+            s.set_variants(1, plain_vertex)
+        ref = plain_steps([inst[i] for i in sample], 3, 0.2)
+        b = fdu.Batch([s for s, _ in inst])
+        b.set_schedule(schedule, 4 if schedule else 16, 8 if schedule else 16, vmode)
+        ws = [w0.clone() for _, w0 in inst]
+        scr = [torch.empty(2 * s.nv_total, 4, dtype=torch.float64, device="cuda") for s, _ in inst]
+        b.set_states(ws, scr)
+        for _ in range(3):
+            b.step(0.2)
+        err, _ = b.status()
+        assert err == 0
+        for k, i in enumerate(sample):
+            assert torch.equal(ws[i].cpu(), ref[k]), (schedule, i)
+        del b
