@@ -34,8 +34,9 @@
  *     cotangent arrays are [nv_real][4] (residual) or [nv_total][4] (state
  *     cotangents).  Edge fluxes are [ne_flux][4] double.
  *   - Vertex and edge numbering inside the library is the prep's order
- *     (reverse Cuthill-McKee of the real vertices when requested); the prep
- *     exposes the permutation so callers can map their arrays.
+ *     (reverse Cuthill-McKee or Hilbert order of the real vertices when
+ *     requested); the prep exposes the permutation so callers can map their
+ *     arrays.
  */
 #ifndef FDU_H
 #define FDU_H

@@ -150,8 +150,8 @@ FDU_HD double weno_eval(const WenoGeom& G, const double u[5], double eps, int po
 
 // ----------------------------------------------------------------------------
 // Forward-mode dual numbers: value plus N directional derivatives.  The frame
-// and flux functions below are templates on the scalar type so the adjoint
-// kernels can take exact Jacobians of them (N = 8: the two states they read).
+// and flux functions below are templates on the scalar type; the adjoint's
+// vertex kernel takes the Euler flux Jacobians with N = 4.
 using ::fabs;
 using ::sqrt;
 

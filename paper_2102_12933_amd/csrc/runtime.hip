@@ -873,6 +873,7 @@ fdu_status fdu_finalize(fdu_solver* s) {
     s->h_cO = c;
     s->cfl_blocks = (int)std::min<int64_t>(1024, (s->nv_real + 255) / 256);
     s->part.alloc(s->cfl_blocks);
+    s->chk.alloc(2);
     build_vertex_blocks(s);
     s->finalized = true;
   });
@@ -896,7 +897,6 @@ fdu_status fdu_check_state(fdu_solver* s, const void* w, int64_t* n_bad, int64_t
     need(w && n_bad && first_bad, "NULL argument");
     DeviceGuard dg(s->device);
     hipStream_t st = (hipStream_t)stream;
-    if (s->chk.n != 2) s->chk.alloc(2);
     hipLaunchKernelGGL(k_check_reset, dim3(1), dim3(64), 0, st, s->chk.p);
     if (s->prec == FDU_F64)
       hipLaunchKernelGGL(k_check_state<double>, dim3(nblocks(s->nv_real)), dim3(256), 0, st, (const double*)w,
