@@ -266,18 +266,20 @@ fdu_status fdu_kernel_times(fdu_solver* s, void* w, void* scratch, int reps, dou
 /* Live kernel timer: measurement aid for the ordinary compute calls.
  * fdu_kernel_timer_start: from now on every launch of the ghost-fill, edge-flux,
  * vertex and CFL kernels by this solver (fdu_fill_ghosts, fdu_edge_fluxes,
- * fdu_residual, fdu_cfl_dt, fdu_rk_stage, fdu_rk_step) is bracketed by a pair
- * of HIP events recorded on the stream of that call, for the first `capacity`
- * (1 .. 2^20) launches of each kind; nothing is recorded while the stream is
- * being captured into a graph.  Creates the events on first use (set-up,
- * synchronous); the solver owns them until fdu_destroy.
+ * fdu_residual, fdu_cfl_dt, fdu_rk_stage, fdu_rk_step) whose kind is selected
+ * by `phases` (bit 0 ghost fill, 1 edge flux, 2 vertex step, 3 CFL; 15 = all)
+ * is bracketed by a pair of timing-only HIP events recorded on the stream of
+ * that call, for the first `capacity` (1 .. 2^20) launches of each kind;
+ * nothing is recorded while the stream is being captured into a graph.
+ * Creates the events on first use (set-up, synchronous); the solver owns them
+ * until fdu_destroy.
  * fdu_kernel_timer_stop: stops recording, waits for the last recorded event and
  * writes, for ghost fill, edge flux, vertex step and CFL reduction in that
  * order, the mean bracketed duration in milliseconds to avg_ms[0..3] and the
  * number of launches timed to counts[0..3] (0 and 0.0 when none).  Returns
  * FDU_ERR_INVALID_ARG when the timer is not running or a pointer is NULL.
  * The event records add a few microseconds per launch to the stream. */
-fdu_status fdu_kernel_timer_start(fdu_solver* s, int capacity);
+fdu_status fdu_kernel_timer_start(fdu_solver* s, int capacity, int phases);
 fdu_status fdu_kernel_timer_stop(fdu_solver* s, double* avg_ms, int* counts);
 
 /* ------------------------------------------------------------------------
@@ -323,6 +325,7 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
  * (the parity tests run each one); they differ in schedule and register use:
  *   edge:   0 = coefficient-form WENO, IEEE divisions; 1 = divided-difference
  *           WENO, one side's geometry live at a time, refined reciprocals;
+ *           2 = variant 1 with its registers held to 4 waves per SIMD;
  *   vertex: 0 = 16 lanes per vertex, strided loops; 1, 2, 3 = 16, 32, 8 lanes
  *           per vertex, all index/weight loads issued before all gathers;
  *           4, 5 = strided loops with 8 and 4 lanes per vertex; 6, 7 = strided
@@ -333,7 +336,13 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
  *           10, 11 = 8 and 4 lanes per vertex over vertex blocks whose
  *           stencil halo (state and flux rows) is first staged in LDS, 16-bit
  *           block-local row indices (blocks are built at fdu_finalize; they
- *           are compact when the prep used the Hilbert order, reorder = 2).
+ *           are compact when the prep used the Hilbert order, reorder = 2);
+ *           12, 13 = variants 10 and 11 with each XCD's range of blocks walked
+ *           from its end (the rows the edge kernel wrote last come first);
+ *           14, 15 = the blocks of variant 10 with their CSR pointers and own
+ *           state rows also staged in LDS and the stage combine spread over 4
+ *           lanes (15: the next round's index and weight loads issued before
+ *           the current round is computed).
  * fdu_set_variants / fdu_get_variants select and report them (n_edge, n_vertex:
  * how many exist); a new solver starts with edge 1 and vertex 3.  fdu_autotune times every edge variant and then every vertex
  * variant on the given state with fdu_kernel_times (reps launches each),

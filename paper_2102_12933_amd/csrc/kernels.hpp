@@ -54,14 +54,6 @@ __device__ __forceinline__ void store4(float* __restrict__ w, int v, const doubl
   reinterpret_cast<float4*>(w)[v] = make_float4((float)q[0], (float)q[1], (float)q[2], (float)q[3]);
 }
 
-// Euler fluxes f, g of a conservative state (Sec. 2.1).
-FDU_HD void euler_fg(const double q[4], double gm1, double f[4], double g[4]) {
-  const double ir = 1.0 / q[0];
-  const double u = q[1] * ir, v = q[2] * ir;
-  const double p = gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * v));
-  f[0] = q[1]; f[1] = q[1] * u + p; f[2] = q[1] * v; f[3] = (q[3] + p) * u;
-  g[0] = q[2]; g[1] = q[2] * u;     g[2] = q[2] * v + p; g[3] = (q[3] + p) * v;
-}
 
 // Reciprocal: the hardware estimate (relative error ~5e-8 on gfx950) refined by
 // one Newton step (~2e-15 relative, 10 ulp at most over a 2^20-sample sweep
@@ -71,6 +63,19 @@ __device__ __forceinline__ double frcp(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
+// Square root of x > 0 (normal range): the hardware reciprocal square root
+// estimate r ~ (1 + d)/sqrt(x), then one Goldschmidt step (y = x r, h = r/2,
+// e = 1/2 - y h; y += y e, h += h e: error O(d^2)) and one residual correction
+// y += h (x - y^2) (error O(d^3) plus rounding).
+__device__ __forceinline__ double fsqrt(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  double y = x * r, h = 0.5 * r;
+  const double e = fma(-y, h, 0.5);
+  y = fma(y, e, y);
+  h = fma(h, e, h);
+  return fma(fma(-y, y, x), h, y);
+}
+
 // 1/x: IEEE division, or (FR, device code) the refined hardware reciprocal.
 template <bool FR>
 FDU_HD double recip(double x) {
@@ -78,6 +83,55 @@ FDU_HD double recip(double x) {
   if (FR) return frcp(x);
 #endif
   return 1.0 / x;
+}
+
+// sqrt(x): the library square root, or (FR, device code) fsqrt.
+template <bool FR>
+FDU_HD double root(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (FR) return fsqrt(x);
+#endif
+  return sqrt(x);
+}
+
+// Euler fluxes f, g of a conservative state (Sec. 2.1); FR: 1/rho from the
+// refined hardware reciprocal.
+template <bool FR = false>
+FDU_HD void euler_fg(const double q[4], double gm1, double f[4], double g[4]) {
+  const double ir = recip<FR>(q[0]);
+  const double u = q[1] * ir, v = q[2] * ir;
+  const double p = gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * v));
+  f[0] = q[1]; f[1] = q[1] * u + p; f[2] = q[1] * v; f[3] = (q[3] + p) * u;
+  g[0] = q[2]; g[1] = q[2] * u;     g[2] = q[2] * v + p; g[3] = (q[3] + p) * v;
+}
+
+// Sum over aligned groups of LPV consecutive lanes (LPV = 2, 4, 8 or 16),
+// every lane of a group receiving the group's sum: DPP lane permutations
+// within a row of 16 lanes (mirror, half-row mirror, quad swaps), no LDS
+// traffic.  The four steps pair disjoint lane sets, so each lane's value
+// enters once.  All lanes of the wave must execute it.
+__device__ __forceinline__ double dpp_add(double x, int ctrl_sel) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  switch (ctrl_sel) {
+    case 0: lo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false);   // row mirror
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false); break;
+    case 1: lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false);   // half-row mirror
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false); break;
+    case 2: lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);    // quad_perm(2, 3, 0, 1)
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false); break;
+    default: lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);   // quad_perm(1, 0, 3, 2)
+             hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+  }
+  return x + __hiloint2double(hi, lo);
+}
+
+template <int LPV>
+__device__ __forceinline__ double group_sum(double x) {
+  static_assert(LPV == 2 || LPV == 4 || LPV == 8 || LPV == 16, "group of 2, 4, 8 or 16 lanes");
+  if (LPV >= 16) x = dpp_add(x, 0);
+  if (LPV >= 8) x = dpp_add(x, 1);
+  if (LPV >= 4) x = dpp_add(x, 2);
+  return dpp_add(x, 3);
 }
 
 // Opaque copy of a value: the compiler cannot merge a computation on it with
@@ -227,6 +281,8 @@ FDU_HD double val(double x) { return x; }
 template <int N> FDU_HD double val(const Dual<N>& x) { return x.v; }
 template <bool FR, int N>
 FDU_HD Dual<N> recip(const Dual<N>& x) { return 1.0 / x; }
+template <bool FR, int N>
+FDU_HD Dual<N> root(const Dual<N>& x) { return sqrt(x); }
 
 // ----------------------------------------------------------------------------
 // Eigenvectors of A_n = n_x df/dw + n_y dg/dw at a Roe-averaged state:
@@ -242,7 +298,7 @@ using Frame = FrameT<double>;
 template <class T, bool FR = false>
 FDU_HD FrameT<T> roe_frame(const T a[4], const T b[4], double nx, double ny, double gm1) {
   FrameT<T> F;
-  const T ra = sqrt(a[0]), rb = sqrt(b[0]);
+  const T ra = root<FR>(a[0]), rb = root<FR>(b[0]);
   const T ia = recip<FR>(a[0]), ib = recip<FR>(b[0]);
   const T ua = a[1] * ia, va = a[2] * ia, ub = b[1] * ib, vb = b[2] * ib;
   const T pa = gm1 * (a[3] - 0.5 * (a[1] * ua + a[2] * va));
@@ -253,7 +309,7 @@ FDU_HD FrameT<T> roe_frame(const T a[4], const T b[4], double nx, double ny, dou
   F.v = (ra * va + rb * vb) * is;
   F.H = (ra * Ha + rb * Hb) * is;
   F.q2 = 0.5 * (F.u * F.u + F.v * F.v);
-  F.c = sqrt(gm1 * (F.H - F.q2));
+  F.c = root<FR>(gm1 * (F.H - F.q2));
   F.nx = nx;
   F.ny = ny;
   F.un = F.u * nx + F.v * ny;
@@ -325,7 +381,7 @@ FDU_HD void riemann_flux(const T wl[4], const T wr[4], double nx, double ny, con
   normal_flux<T, FR>(wl, nx, ny, S.gm1, Fl, unl, c2l);
   normal_flux<T, FR>(wr, nx, ny, S.gm1, Fr, unr, c2r);
   if (S.riemann == 1) {
-    const T sl = fabs(unl) + sqrt(c2l), sr = fabs(unr) + sqrt(c2r);
+    const T sl = fabs(unl) + root<FR>(c2l), sr = fabs(unr) + root<FR>(c2r);
     const T sm = val(sl) >= val(sr) ? sl : sr;
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[k] = 0.5 * (Fl[k] + Fr[k]) - 0.5 * sm * (wr[k] - wl[k]);
@@ -405,6 +461,15 @@ FDU_HD void edge_flux_one(const double W[6][4], const double g[6], const Scheme&
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   const int q = nb >> 3, r = nb & 7, x = b & 7;
   return x * q + min(x, r) + (b >> 3);
+}
+
+// The same ranges per XCD, each walked from its end: a kernel launched after
+// one that used xcd_block starts on the rows the previous kernel touched last
+// (still in the XCD's L2 and the memory-side cache).
+__device__ __forceinline__ int xcd_block_rev(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  const int len = q + (x < r ? 1 : 0);
+  return x * q + min(x, r) + (len - 1 - (b >> 3));
 }
 
 // ----------------------------------------------------------------------------
@@ -565,22 +630,41 @@ struct WenoDD {
   double C[3];
 };
 
+// The eight node gaps a side needs are positive and of moderate size (they are
+// normalised by the middle-edge length), so their inverses come from one
+// reciprocal of their product (prefix products, then one multiplication back
+// per gap: 1/a_i = (1/(a_1..a_i)) (a_1..a_{i-1})).
 __device__ __forceinline__ void weno_dd_geom(double x0, double x1, double x4, WenoDD& G) {
   G.x0 = x0; G.x1 = x1; G.x4 = x4;
-  G.ig[0] = frcp(x1 - x0);
-  G.ig[1] = frcp(-0.5 - x1);
+  const double a[8] = {x1 - x0, -0.5 - x1, x4 - 0.5, -0.5 - x0, 0.5 - x1, x4 + 0.5, x4 - x0, (0.5 - x0) * (x4 - x1)};
+  double p[8];
+  p[0] = a[0];
+#pragma unroll
+  for (int i = 1; i < 8; ++i) p[i] = p[i - 1] * a[i];
+  double inv = frcp(p[7]), ia[8];
+#pragma unroll
+  for (int i = 7; i > 0; --i) {
+    ia[i] = inv * p[i - 1];
+    inv *= a[i];
+  }
+  ia[0] = inv;
+  G.ig[0] = ia[0];
+  G.ig[1] = ia[1];
   G.ig[2] = 1.0;
-  G.ig[3] = frcp(x4 - 0.5);
-  G.ih[0] = frcp(-0.5 - x0);
-  G.ih[1] = frcp(0.5 - x1);
-  G.ih[2] = frcp(x4 + 0.5);
-  const double i40 = frcp(x4 - x0);
-  G.C[0] = 0.5 * x4 * i40 * frcp(0.5 - x0);
-  G.C[2] = x0 * x1 * i40 * frcp(x4 - x1);
+  G.ig[3] = ia[2];
+  G.ih[0] = ia[3];
+  G.ih[1] = ia[4];
+  G.ih[2] = ia[5];
+  // C0 = x3 x4 / ((x4 - x0)(x3 - x0)), C2 = x0 x1 / ((x4 - x0)(x4 - x1)), x3 = 1/2
+  const double t = ia[6] * ia[7];
+  G.C[0] = 0.5 * x4 * (x4 - x1) * t;
+  G.C[2] = x0 * x1 * (0.5 - x0) * t;
   G.C[1] = 1.0 - G.C[0] - G.C[2];
 }
 
-__device__ __forceinline__ double weno_dd_eval(const WenoDD& G, const double u[5], double eps, int power) {
+// POW: the power of the smoothness indicators in the weights (1 or 2).
+template <int POW>
+__device__ __forceinline__ double weno_dd_eval(const WenoDD& G, const double u[5], double eps) {
   const double xs[5] = {G.x0, G.x1, -0.5, 0.5, G.x4};
   double dd[4];
 #pragma unroll
@@ -592,9 +676,9 @@ __device__ __forceinline__ double weno_dd_eval(const WenoDD& G, const double u[5
     const double h2 = (dd[k + 1] - dd[k]) * G.ih[k];          // q''/2
     const double d1 = dd[k] - h2 * (a + bb);                   // q'(0)
     ut[k] = u[k] - dd[k] * a + h2 * a * bb;                    // q(0)
-    const double q2 = 2.0 * h2;
-    b[k] = d1 * d1 + (13.0 / 12.0) * q2 * q2 + eps;
-    if (power == 2) b[k] *= b[k];
+    // q'(0)^2 + (13/12) q''^2 with q'' = 2 h2
+    b[k] = fma(d1, d1, fma((13.0 / 3.0) * h2, h2, eps));
+    if (POW == 2) b[k] *= b[k];
   }
   const double n0 = G.C[0] * b[1] * b[2];
   const double n1 = G.C[1] * b[0] * b[2];
@@ -603,9 +687,9 @@ __device__ __forceinline__ double weno_dd_eval(const WenoDD& G, const double u[5
 }
 
 // Edge flux, register-lean variant: one side's WENO geometry live at a time,
-// divided-difference interpolants, refined reciprocals.
-template <class T, class TG>
-__device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const int* __restrict__ sten,
+// divided-difference interpolants, refined reciprocals and square roots.
+template <class T, class TG, int POW>
+__device__ __forceinline__ void edge_lean_body(const T* __restrict__ w, const int* __restrict__ sten,
                                                const TG* __restrict__ geo, double* __restrict__ r, int e,
                                                const Scheme& S) {
   int id[6];
@@ -645,7 +729,7 @@ __device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const in
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double u[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
-      cl[c] = weno_dd_eval(G, u, S.eps, S.power);
+      cl[c] = weno_dd_eval<POW>(G, u, S.eps);
     }
   }
   {
@@ -654,7 +738,7 @@ __device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const in
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double u[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
-      cr[c] = weno_dd_eval(G, u, S.eps, S.power);
+      cr[c] = weno_dd_eval<POW>(G, u, S.eps);
     }
   }
   double wl[4], wr[4];
@@ -669,12 +753,9 @@ __device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const in
     from_char(F, cr, wr);
   }
   if (S.positivity) {
-    if (!physical<true>(wl, S.gm1))
-#pragma unroll
-      for (int k = 0; k < 4; ++k) wl[k] = W2[k];
-    if (!physical<true>(wr, S.gm1))
-#pragma unroll
-      for (int k = 0; k < 4; ++k) wr[k] = W3[k];
+    // the end states are reloaded (rarely needed; not kept live in registers)
+    if (!physical<true>(wl, S.gm1)) load4(w, opaque(id[2]), wl);
+    if (!physical<true>(wr, S.gm1)) load4(w, opaque(id[3]), wr);
   }
   double out[4];
   riemann_flux<double, true>(wl, wr, nx, ny, S, out);
@@ -683,10 +764,23 @@ __device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const in
   rp[1] = make_double2(out[2], out[3]);
 }
 
+// The WENO power is uniform over a launch: one branch instead of a select per
+// smoothness indicator.
 template <class T, class TG>
-__global__ void __launch_bounds__(256) k_edge_flux_lean(const T* __restrict__ w, const int* __restrict__ sten,
-                                                        const TG* __restrict__ geo, double* __restrict__ r, int ne,
-                                                        Scheme S) {
+__device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const int* __restrict__ sten,
+                                               const TG* __restrict__ geo, double* __restrict__ r, int e,
+                                               const Scheme& S) {
+  if (S.power == 2)
+    edge_lean_body<T, TG, 2>(w, sten, geo, r, e, S);
+  else
+    edge_lean_body<T, TG, 1>(w, sten, geo, r, e, S);
+}
+
+// WPE: waves per SIMD the register allocation is held to (1: unconstrained).
+template <class T, class TG, int WPE>
+__global__ void __launch_bounds__(256, WPE) k_edge_flux_lean(const T* __restrict__ w, const int* __restrict__ sten,
+                                                             const TG* __restrict__ geo, double* __restrict__ r,
+                                                             int ne, Scheme S) {
   const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (e < ne) edge_lean_item<T, TG>(w, sten, geo, r, e, S);
 }
@@ -1009,7 +1103,7 @@ __device__ __forceinline__ void vertex_lds_compute(const VertexFetch<TW, MV, ME>
   const int vv = active ? v : v0;
   double q0[4], f0[4], g0[4];
   load4(w, vv, q0);
-  euler_fg(q0, gm1, f0, g0);
+  euler_fg<true>(q0, gm1, f0, g0);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int s = 0; s < MV; ++s) {
@@ -1018,7 +1112,7 @@ __device__ __forceinline__ void vertex_lds_compute(const VertexFetch<TW, MV, ME>
       const double2 x = lp[0], y = lp[1];
       const double q[4] = {x.x, x.y, y.x, y.y};
       double f[4], g[4];
-      euler_fg(q, gm1, f, g);
+      euler_fg<true>(q, gm1, f, g);
 #pragma unroll
       for (int k = 0; k < 4; ++k) acc[k] += F.wf[s] * (f[k] - f0[k]) + F.wg[s] * (g[k] - g0[k]);
     }
@@ -1037,7 +1131,7 @@ __device__ __forceinline__ void vertex_lds_compute(const VertexFetch<TW, MV, ME>
     const double q[4] = {x.x, x.y, y.x, y.y};
     const double af = (double)wfg[2 * (size_t)p], ag = (double)wfg[2 * (size_t)p + 1];
     double f[4], g[4];
-    euler_fg(q, gm1, f, g);
+    euler_fg<true>(q, gm1, f, g);
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[k] += af * (f[k] - f0[k]) + ag * (g[k] - g0[k]);
   }
@@ -1048,10 +1142,7 @@ __device__ __forceinline__ void vertex_lds_compute(const VertexFetch<TW, MV, ME>
     acc[0] += c * x.x; acc[1] += c * x.y; acc[2] += c * y.x; acc[3] += c * y.y;
   }
 #pragma unroll
-  for (int m = LPV / 2; m >= 1; m >>= 1) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] += __shfl_xor(acc[k], m, LPV);
-  }
+  for (int k = 0; k < 4; ++k) acc[k] = group_sum<LPV>(acc[k]);
   if (active && lane == 0) {
     const double cx = cO[2 * (size_t)v], cy = cO[2 * (size_t)v + 1];
     double res[4];
@@ -1136,10 +1227,200 @@ __global__ void __launch_bounds__(256, WPE) k_vertex_lds(const T* __restrict__ w
                                                          const double* __restrict__ r, double gm1, int mode,
                                                          T* __restrict__ R, const T* __restrict__ wn,
                                                          T* __restrict__ out, double a, double b,
-                                                         const double* __restrict__ dt_dev) {
+                                                         const double* __restrict__ dt_dev, int rev) {
   extern __shared__ double lds[];   // [rows][4]: the block's state rows, then its flux rows
-  vertex_lds_block<T, TW, LPV, MV, ME, PF>(xcd_block(blockIdx.x, gridDim.x), lds, w, blk, uvp, uv, uep, ue, vptr,
+  const int bk = rev ? xcd_block_rev(blockIdx.x, gridDim.x) : xcd_block(blockIdx.x, gridDim.x);
+  vertex_lds_block<T, TW, LPV, MV, ME, PF>(bk, lds, w, blk, uvp, uv, uep, ue, vptr,
                                            lvcol, wfg, eptr, lecol, we, cO, r, gm1, mode, R, wn, out, a, b, dt_dev);
+}
+
+// Vertex step over the same vertex blocks with more of the block in LDS: the
+// block's CSR pointers and its own state rows (consecutive in its state-row
+// list, starting at own[block]) are staged with the halo, so the only global
+// loads of a round are the stream of 16-bit local ids and weights (with
+// PF = 2 issued before the previous round is computed: no pointer load sits in
+// front of them), and the stage combine is done by lanes 0-3 of each vertex,
+// one component each (8-byte loads and stores instead of 32-byte rows).  The
+// arithmetic is that of k_vertex_lds with the same lanes, term for term.
+template <class TW, int MV, int ME>
+struct BlockFetch {
+  int i, pb, pe, qb, qe;
+  int jv[MV], ke[ME];
+  double wf[MV], wg[MV], cw[ME];
+};
+
+template <class TW, int LPV, int MV, int ME>
+__device__ __forceinline__ void block_fetch(BlockFetch<TW, MV, ME>& F, int i, int nb, int lane,
+                                            const int* __restrict__ lp, const unsigned short* __restrict__ lvcol,
+                                            const TW* __restrict__ wfg, const unsigned short* __restrict__ lecol,
+                                            const TW* __restrict__ we) {
+  F.i = i;
+  F.pb = F.pe = F.qb = F.qe = 0;
+  if (i < nb) {
+    F.pb = lp[i]; F.pe = lp[i + 1];
+    F.qb = lp[nb + 1 + i]; F.qe = lp[nb + 2 + i];
+  }
+#pragma unroll
+  for (int s = 0; s < MV; ++s) {
+    const int p = F.pb + lane + s * LPV;
+    F.jv[s] = p < F.pe ? (int)lvcol[p] : -1;
+    F.wf[s] = p < F.pe ? (double)wfg[2 * (size_t)p] : 0.0;
+    F.wg[s] = p < F.pe ? (double)wfg[2 * (size_t)p + 1] : 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < ME; ++s) {
+    const int p = F.qb + lane + s * LPV;
+    F.ke[s] = p < F.qe ? (int)lecol[p] : -1;
+    F.cw[s] = p < F.qe ? (double)we[p] : 0.0;
+  }
+}
+
+__device__ __forceinline__ double pick4(const double x[4], int k) {
+  return k == 0 ? x[0] : (k == 1 ? x[1] : (k == 2 ? x[2] : x[3]));
+}
+
+template <class T, class TW, int LPV, int MV, int ME>
+__device__ __forceinline__ void block_compute(const BlockFetch<TW, MV, ME>& F, int v0, int nb, int o0, int lane,
+                                              const double* __restrict__ Lv, const double* __restrict__ Le,
+                                              const unsigned short* __restrict__ lvcol, const TW* __restrict__ wfg,
+                                              const unsigned short* __restrict__ lecol, const TW* __restrict__ we,
+                                              const double* __restrict__ cO, double gm1, int mode,
+                                              T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
+                                              double a, double b, const double* __restrict__ dt_dev) {
+  const bool active = F.i < nb;
+  const double* own = Lv + 4 * (o0 + (active ? F.i : 0));
+  double q0[4], f0[4], g0[4];
+  {
+    const double2* lp = reinterpret_cast<const double2*>(own);
+    const double2 x = lp[0], y = lp[1];
+    q0[0] = x.x; q0[1] = x.y; q0[2] = y.x; q0[3] = y.y;
+  }
+  euler_fg<true>(q0, gm1, f0, g0);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < MV; ++s) {
+    if (F.jv[s] >= 0) {
+      const double2* lp = reinterpret_cast<const double2*>(Lv + 4 * F.jv[s]);
+      const double2 x = lp[0], y = lp[1];
+      const double q[4] = {x.x, x.y, y.x, y.y};
+      double f[4], g[4];
+      euler_fg<true>(q, gm1, f, g);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] += F.wf[s] * (f[k] - f0[k]) + F.wg[s] * (g[k] - g0[k]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < ME; ++s) {
+    if (F.ke[s] >= 0) {
+      const double2* lp = reinterpret_cast<const double2*>(Le + 4 * F.ke[s]);
+      const double2 x = lp[0], y = lp[1];
+      acc[0] += F.cw[s] * x.x; acc[1] += F.cw[s] * x.y; acc[2] += F.cw[s] * y.x; acc[3] += F.cw[s] * y.y;
+    }
+  }
+  for (int p = F.pb + lane + MV * LPV; p < F.pe; p += LPV) {
+    const double2* lp = reinterpret_cast<const double2*>(Lv + 4 * (int)lvcol[p]);
+    const double2 x = lp[0], y = lp[1];
+    const double q[4] = {x.x, x.y, y.x, y.y};
+    const double af = (double)wfg[2 * (size_t)p], ag = (double)wfg[2 * (size_t)p + 1];
+    double f[4], g[4];
+    euler_fg<true>(q, gm1, f, g);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += af * (f[k] - f0[k]) + ag * (g[k] - g0[k]);
+  }
+  for (int p = F.qb + lane + ME * LPV; p < F.qe; p += LPV) {
+    const double2* lp = reinterpret_cast<const double2*>(Le + 4 * (int)lecol[p]);
+    const double2 x = lp[0], y = lp[1];
+    const double c = (double)we[p];
+    acc[0] += c * x.x; acc[1] += c * x.y; acc[2] += c * y.x; acc[3] += c * y.y;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) acc[k] = group_sum<LPV>(acc[k]);
+  if (active && lane < 4) {
+    const int k = lane;
+    const size_t v = (size_t)(v0 + F.i);
+    const double cx = cO[2 * v], cy = cO[2 * v + 1];
+    const double res = -(pick4(acc, k) - (cx * pick4(f0, k) + cy * pick4(g0, k)));
+    if (mode == 0) {
+      R[4 * v + k] = (T)res;
+    } else {
+      const double dt = *dt_dev;
+      const double n = a != 0.0 ? (double)wn[4 * v + k] : 0.0;
+      out[4 * v + k] = (T)(a * n + b * (own[k] + dt * res));
+    }
+  }
+}
+
+template <class T, class TW, int LPV, int MV, int ME, int PF>
+__device__ __forceinline__ void vertex_block2(int bk, double* lds, const T* __restrict__ w, const int* __restrict__ blk,
+                                              const int* __restrict__ own, const int* __restrict__ uvp,
+                                              const int* __restrict__ uv, const int* __restrict__ uep,
+                                              const int* __restrict__ ue, const int* __restrict__ vptr,
+                                              const unsigned short* __restrict__ lvcol, const TW* __restrict__ wfg,
+                                              const int* __restrict__ eptr, const unsigned short* __restrict__ lecol,
+                                              const TW* __restrict__ we, const double* __restrict__ cO,
+                                              const double* __restrict__ r, double gm1, int mode,
+                                              T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
+                                              double a, double b, const double* __restrict__ dt_dev) {
+  constexpr int VPR = 256 / LPV;    // vertices per round
+  const int v0 = blk[bk], nb = blk[bk + 1] - v0;
+  const int a0 = uvp[bk], na = uvp[bk + 1] - a0;
+  const int e0 = uep[bk], ne = uep[bk + 1] - e0;
+  const int o0 = own[bk];
+  const int lane = threadIdx.x % LPV, sub = threadIdx.x / LPV;
+  int* lp = reinterpret_cast<int*>(lds + 4 * (na + ne));   // vptr[v0 .. v0 + nb], then eptr[v0 .. v0 + nb]
+  for (int i = threadIdx.x; i < na; i += blockDim.x) {
+    double q[4];
+    load4(w, uv[a0 + i], q);
+    double2* d = reinterpret_cast<double2*>(lds + 4 * i);
+    d[0] = make_double2(q[0], q[1]);
+    d[1] = make_double2(q[2], q[3]);
+  }
+  for (int i = threadIdx.x; i < ne; i += blockDim.x) {
+    const double2* sp = reinterpret_cast<const double2*>(r + 4 * (size_t)ue[e0 + i]);
+    double2* d = reinterpret_cast<double2*>(lds + 4 * (na + i));
+    d[0] = sp[0];
+    d[1] = sp[1];
+  }
+  for (int i = threadIdx.x; i <= nb; i += blockDim.x) {
+    lp[i] = vptr[v0 + i];
+    lp[nb + 1 + i] = eptr[v0 + i];
+  }
+  __syncthreads();
+  const double* Lv = lds;
+  const double* Le = lds + 4 * na;
+  BlockFetch<TW, MV, ME> F;
+  block_fetch<TW, LPV, MV, ME>(F, sub, nb, lane, lp, lvcol, wfg, lecol, we);
+  for (int ib = 0; ib < nb; ib += VPR) {
+    if (PF == 2) {
+      BlockFetch<TW, MV, ME> G;
+      block_fetch<TW, LPV, MV, ME>(G, ib + VPR + sub, nb, lane, lp, lvcol, wfg, lecol, we);
+      block_compute<T, TW, LPV, MV, ME>(F, v0, nb, o0, lane, Lv, Le, lvcol, wfg, lecol, we, cO, gm1, mode, R, wn, out,
+                                        a, b, dt_dev);
+      F = G;
+    } else {
+      if (ib > 0) block_fetch<TW, LPV, MV, ME>(F, ib + sub, nb, lane, lp, lvcol, wfg, lecol, we);
+      block_compute<T, TW, LPV, MV, ME>(F, v0, nb, o0, lane, Lv, Le, lvcol, wfg, lecol, we, cO, gm1, mode, R, wn, out,
+                                        a, b, dt_dev);
+    }
+  }
+}
+
+template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE>
+__global__ void __launch_bounds__(256, WPE) k_vertex_blk(const T* __restrict__ w, const int* __restrict__ blk,
+                                                         const int* __restrict__ own, const int* __restrict__ uvp,
+                                                         const int* __restrict__ uv, const int* __restrict__ uep,
+                                                         const int* __restrict__ ue, const int* __restrict__ vptr,
+                                                         const unsigned short* __restrict__ lvcol,
+                                                         const TW* __restrict__ wfg, const int* __restrict__ eptr,
+                                                         const unsigned short* __restrict__ lecol,
+                                                         const TW* __restrict__ we, const double* __restrict__ cO,
+                                                         const double* __restrict__ r, double gm1, int mode,
+                                                         T* __restrict__ R, const T* __restrict__ wn,
+                                                         T* __restrict__ out, double a, double b,
+                                                         const double* __restrict__ dt_dev) {
+  extern __shared__ double lds[];   // [rows][4] state then flux rows, then the block's CSR pointers
+  vertex_block2<T, TW, LPV, MV, ME, PF>(xcd_block(blockIdx.x, gridDim.x), lds, w, blk, own, uvp, uv, uep, ue, vptr,
+                                        lvcol, wfg, eptr, lecol, we, cO, r, gm1, mode, R, wn, out, a, b, dt_dev);
 }
 
 // State check: counts real rows that are not finite or not physical
@@ -1166,10 +1447,16 @@ __global__ void k_check_reset(unsigned long long* out) {
 
 // CFL time step: per-block minima of hmin_v / (|u_v| + c_v), then one block
 // reduces them and writes cfl * min.
+// CFL step in one launch: block minima to part[], then the last block to
+// arrive (a ticket counter, reset by that block for the next launch) takes the
+// minimum of all of them.  The minimum does not depend on the order, so dt is
+// the same as from a two-pass reduction.
 template <class T>
-__global__ void __launch_bounds__(256) k_cfl_partial(const T* __restrict__ w, const double* __restrict__ hmin, int nreal,
-                                                     double gamma, double* __restrict__ part) {
+__global__ void __launch_bounds__(256) k_cfl(const T* __restrict__ w, const double* __restrict__ hmin, int nreal,
+                                             double gamma, double cfl, double* __restrict__ part,
+                                             unsigned int* __restrict__ ticket, double* __restrict__ dt) {
   __shared__ double sm[256];
+  __shared__ int last;
   double best = 1e300;
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nreal; v += gridDim.x * blockDim.x) {
     double q[4];
@@ -1186,21 +1473,27 @@ __global__ void __launch_bounds__(256) k_cfl_partial(const T* __restrict__ w, co
     if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
-}
-
-__global__ void __launch_bounds__(256) k_cfl_final(const double* __restrict__ part, int n, double cfl,
-                                                   double* __restrict__ dt) {
-  __shared__ double sm[256];
-  double best = 1e300;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) best = fmin(best, part[i]);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sm[0];
+    __threadfence();
+    last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  best = 1e300;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
+    best = fmin(best, __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   sm[threadIdx.x] = best;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) dt[0] = cfl * sm[0];
+  if (threadIdx.x == 0) {
+    dt[0] = cfl * sm[0];
+    *ticket = 0u;
+  }
 }
 
 }  // namespace fdu

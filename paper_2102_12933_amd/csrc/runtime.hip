@@ -77,21 +77,23 @@ struct fdu_solver {
   DevBuf<float> geo32, wfg32, we32;
   int cfl_blocks = 0;
   // vertex blocks with their stencil halos (LDS-staged vertex variants)
-  DevBuf<int32_t> vblk, vb_uvp, vb_uv, vb_uep, vb_ue;
+  DevBuf<int32_t> vblk, vb_own, vb_uvp, vb_uv, vb_uep, vb_ue;
   DevBuf<uint16_t> vb_lvcol, vb_lecol;
+  DevBuf<uint32_t> cfl_ticket;   // arrival counter of the one-launch CFL reduction (0 between launches)
   int n_vblocks = 0, vb_rows_max = 0;
   // live kernel timer (fdu_kernel_timer_start/stop): event pairs recorded
   // around each launch of the ghost, edge, vertex and CFL kernels
   bool timer_on = false;
-  int timer_cap = 0;
+  int timer_cap = 0, timer_mask = 0;
   int timer_n[4] = {0, 0, 0, 0};
   std::vector<hipEvent_t> timer_ev[4];
   ~fdu_solver() {
     for (auto& v : timer_ev)
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
   }
-  int edge_variant = 1;    // 0: k_edge_flux, 1: k_edge_flux_lean
-  int vertex_variant = 3;  // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair, 10-11: k_vertex_lds
+  int edge_variant = 1;    // 0: k_edge_flux, 1-2: k_edge_flux_lean (2: held to 4 waves per SIMD)
+  int vertex_variant = 3;  // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair,
+                           // 10-13: k_vertex_lds (12-13: blocks walked in reverse), 14-15: k_vertex_blk
 };
 
 namespace {
@@ -154,7 +156,7 @@ void launch_check() { FDU_HIP(hipGetLastError()); }
 // is on and has room (never while the stream is being captured).
 template <class F>
 void timed_launch(fdu_solver* s, int phase, hipStream_t st, F&& launch) {
-  bool rec = s->timer_on && s->timer_n[phase] < s->timer_cap;
+  bool rec = s->timer_on && ((s->timer_mask >> phase) & 1) && s->timer_n[phase] < s->timer_cap;
   if (rec) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     FDU_HIP(hipStreamIsCapturing(st, &cs));
@@ -180,15 +182,19 @@ void fill_ghosts_t(fdu_solver* s, T* w, hipStream_t st) {
   launch_check();
 }
 
-constexpr int kEdgeVariants = 2;
-constexpr int kVertexVariants = 12;
+constexpr int kBlockVertices = 256;   // vertex blocks: at most this many vertices
+constexpr int kBlockRows = 768;       // and this many staged rows (24 KB of LDS)
+constexpr int kEdgeVariants = 3;
+constexpr int kVertexVariants = 16;
 
 template <class T, class TG>
 void edge_flux_launch(fdu_solver* s, const T* w, const TG* geo, double* r, hipStream_t st) {
   const Scheme S = scheme_of(s);
   const dim3 grid(nblocks(s->ne_flux)), block(256);
   if (s->edge_variant == 1)
-    hipLaunchKernelGGL((k_edge_flux_lean<T, TG>), grid, block, 0, st, w, s->sten.p, geo, r, (int)s->ne_flux, S);
+    hipLaunchKernelGGL((k_edge_flux_lean<T, TG, 1>), grid, block, 0, st, w, s->sten.p, geo, r, (int)s->ne_flux, S);
+  else if (s->edge_variant == 2)
+    hipLaunchKernelGGL((k_edge_flux_lean<T, TG, 4>), grid, block, 0, st, w, s->sten.p, geo, r, (int)s->ne_flux, S);
   else
     hipLaunchKernelGGL((k_edge_flux<T, TG>), grid, block, 0, st, w, s->sten.p, geo, r, (int)s->ne_flux, S);
 }
@@ -225,12 +231,23 @@ void vertex_pair_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, 
 
 template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE>
 void vertex_lds_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
-                       double a, double b, const double* dt, hipStream_t st) {
+                       double a, double b, const double* dt, hipStream_t st, int rev = 0) {
   if (s->n_vblocks == 0) return;
   const size_t lds = (size_t)s->vb_rows_max * 4 * sizeof(double);
   hipLaunchKernelGGL((k_vertex_lds<T, TW, LPV, MV, ME, PF, WPE>), dim3(s->n_vblocks), dim3(256), lds, st, w, s->vblk.p,
                      s->vb_uvp.p, s->vb_uv.p, s->vb_uep.p, s->vb_ue.p, s->vptr.p, s->vb_lvcol.p, wfg, s->eptr.p,
-                     s->vb_lecol.p, we, s->cO.p, s->flux.p, s->params.gamma - 1.0, mode, R, wn, out, a, b, dt);
+                     s->vb_lecol.p, we, s->cO.p, s->flux.p, s->params.gamma - 1.0, mode, R, wn, out, a, b, dt, rev);
+}
+
+template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE>
+void vertex_blk_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
+                       double a, double b, const double* dt, hipStream_t st) {
+  if (s->n_vblocks == 0) return;
+  const size_t lds = (size_t)s->vb_rows_max * 4 * sizeof(double) + 2 * (kBlockVertices + 1) * sizeof(int);
+  hipLaunchKernelGGL((k_vertex_blk<T, TW, LPV, MV, ME, PF, WPE>), dim3(s->n_vblocks), dim3(256), lds, st, w,
+                     s->vblk.p, s->vb_own.p, s->vb_uvp.p, s->vb_uv.p, s->vb_uep.p, s->vb_ue.p, s->vptr.p,
+                     s->vb_lvcol.p, wfg, s->eptr.p, s->vb_lecol.p, we, s->cO.p, s->flux.p, s->params.gamma - 1.0, mode,
+                     R, wn, out, a, b, dt);
 }
 
 template <class T, class TW, int LPV, bool NT>
@@ -257,6 +274,10 @@ void vertex_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int m
     case 9: vertex_pair_launch<T, TW, 8, 5, 11>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
     case 10: vertex_lds_launch<T, TW, 8, 3, 6, 1, 5>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
     case 11: vertex_lds_launch<T, TW, 4, 5, 11, 1, 4>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 12: vertex_lds_launch<T, TW, 8, 3, 6, 1, 5>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st, 1); break;
+    case 13: vertex_lds_launch<T, TW, 4, 5, 11, 1, 4>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st, 1); break;
+    case 14: vertex_blk_launch<T, TW, 8, 3, 6, 1, 5>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 15: vertex_blk_launch<T, TW, 8, 3, 6, 2, 4>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
     default: vertex_loop_launch<T, TW, 16, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st);
   }
 }
@@ -276,10 +297,8 @@ void vertex_t(fdu_solver* s, const T* w, int mode, T* R, const T* wn, T* out, do
 template <class T>
 void cfl_t(fdu_solver* s, const T* w, double cfl, double* dt, hipStream_t st) {
   timed_launch(s, 3, st, [&] {
-    hipLaunchKernelGGL(k_cfl_partial<T>, dim3(s->cfl_blocks), dim3(256), 0, st, w, s->hmin.p, (int)s->nv_real,
-                       s->params.gamma, s->part.p);
-    launch_check();
-    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, st, s->part.p, s->cfl_blocks, cfl, dt);
+    hipLaunchKernelGGL(k_cfl<T>, dim3(s->cfl_blocks), dim3(256), 0, st, w, s->hmin.p, (int)s->nv_real,
+                       s->params.gamma, cfl, s->part.p, s->cfl_ticket.p, dt);
   });
   launch_check();
 }
@@ -313,14 +332,14 @@ void rk_step_t(fdu_solver* s, T* w, T* scratch, double cfl, double* dt, hipStrea
 // Vertex blocks for the LDS-staged vertex kernels: consecutive real vertices
 // are grouped greedily (at most kBlockVertices per block) while the union of
 // the state rows and flux rows their stencils read stays within kBlockRows
-// rows (32 bytes each in LDS); each block stores its sorted row lists and every
-// stencil entry the 16-bit position of its row in its block's list.
-constexpr int kBlockVertices = 256;
-constexpr int kBlockRows = 768;
+// rows (32 bytes each in LDS); each block stores its sorted row lists (the state
+// rows always include the block's own vertices, a consecutive run starting at
+// position own[block]) and every stencil entry the 16-bit position of its row
+// in its block's list.
 
 void build_vertex_blocks(fdu_solver* s) {
   const int64_t n = s->nv_real;
-  std::vector<int32_t> blk{0}, uvp{0}, uep{0}, uv, ue;
+  std::vector<int32_t> blk{0}, own, uvp{0}, uep{0}, uv, ue;
   std::vector<uint16_t> lvcol(s->nnz_v), lecol(s->nnz_e);
   std::vector<int32_t> mark_v(s->nv_total, -1), mark_e(s->ne_flux, -1), pos_v(s->nv_total), pos_e(s->ne_flux);
   std::vector<int32_t> cur_v, cur_e;
@@ -331,6 +350,7 @@ void build_vertex_blocks(fdu_solver* s) {
     std::sort(cur_e.begin(), cur_e.end());
     for (size_t i = 0; i < cur_v.size(); ++i) pos_v[cur_v[i]] = (int32_t)i;
     for (size_t i = 0; i < cur_e.size(); ++i) pos_e[cur_e[i]] = (int32_t)i;
+    own.push_back(pos_v[vbeg]);   // the block's own rows: consecutive ids, so consecutive in the sorted list
     for (int64_t v = vbeg; v < vend; ++v) {
       for (int32_t p = s->h_vptr[v]; p < s->h_vptr[v + 1]; ++p) lvcol[p] = (uint16_t)pos_v[s->h_vcol[p]];
       for (int32_t p = s->h_eptr[v]; p < s->h_eptr[v + 1]; ++p) lecol[p] = (uint16_t)pos_e[s->h_ecol[p]];
@@ -346,7 +366,7 @@ void build_vertex_blocks(fdu_solver* s) {
   };
   int32_t id = 0;   // block being filled (marks rows already in it)
   for (int64_t v = 0; v < n; ++v) {
-    int add = 0;
+    int add = mark_v[v] != id;
     for (int32_t p = s->h_vptr[v]; p < s->h_vptr[v + 1]; ++p) add += mark_v[s->h_vcol[p]] != id;
     for (int32_t p = s->h_eptr[v]; p < s->h_eptr[v + 1]; ++p) add += mark_e[s->h_ecol[p]] != id;
     const int64_t nvb = v - blk.back();
@@ -354,6 +374,7 @@ void build_vertex_blocks(fdu_solver* s) {
       close(v);
       ++id;
     }
+    if (mark_v[v] != id) { mark_v[v] = id; cur_v.push_back((int32_t)v); }
     for (int32_t p = s->h_vptr[v]; p < s->h_vptr[v + 1]; ++p) {
       const int32_t j = s->h_vcol[p];
       if (mark_v[j] != id) { mark_v[j] = id; cur_v.push_back(j); }
@@ -367,6 +388,7 @@ void build_vertex_blocks(fdu_solver* s) {
   }
   if (n > blk.back()) close(n);
   s->vblk.upload(blk.data(), blk.size());
+  s->vb_own.upload(own.data(), own.size());
   s->vb_uvp.upload(uvp.data(), uvp.size());
   s->vb_uv.upload(uv.data(), uv.size());
   s->vb_uep.upload(uep.data(), uep.size());
@@ -624,7 +646,7 @@ void batch_stage_vm(fdu_batch* b, int k, hipStream_t st) {
 }
 
 void batch_stage(fdu_batch* b, int k, hipStream_t st) {
-  const int ev = b->inst[0]->edge_variant == 1 ? 1 : 0;
+  const int ev = b->inst[0]->edge_variant >= 1 ? 1 : 0;
   if (ev == 1) {
     if (b->vmode == 3) batch_stage_vm<1, 3>(b, k, st);
     else if (b->vmode == 2) batch_stage_vm<1, 2>(b, k, st);
@@ -873,6 +895,8 @@ fdu_status fdu_finalize(fdu_solver* s) {
     s->h_cO = c;
     s->cfl_blocks = (int)std::min<int64_t>(1024, (s->nv_real + 255) / 256);
     s->part.alloc(s->cfl_blocks);
+    const uint32_t zero = 0;
+    s->cfl_ticket.upload(&zero, 1);
     s->chk.alloc(2);
     build_vertex_blocks(s);
     s->finalized = true;
@@ -1265,19 +1289,22 @@ fdu_status fdu_kernel_times(fdu_solver* s, void* w, void* scratch, int reps, dou
   });
 }
 
-fdu_status fdu_kernel_timer_start(fdu_solver* s, int capacity) {
+fdu_status fdu_kernel_timer_start(fdu_solver* s, int capacity, int phases) {
   return guard([&] {
     ready(s);
     need(capacity > 0 && capacity <= (1 << 20), "capacity must be in [1, 2^20]");
+    need(phases > 0 && phases <= 15, "phases must be a non-empty subset of bits 0-3");
     DeviceGuard dg(s->device);
+    // timing-only events: no system-scope fence (cache writeback) at each record
     for (auto& v : s->timer_ev) {
       while ((int)v.size() < 2 * capacity) {
         hipEvent_t e;
-        FDU_HIP(hipEventCreate(&e));
+        FDU_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         v.push_back(e);
       }
     }
     s->timer_cap = capacity;
+    s->timer_mask = phases;
     for (int& n : s->timer_n) n = 0;
     s->timer_on = true;
   });

@@ -65,7 +65,7 @@ _SIGS = {
     "fdu_rk_stage": (I32, [VP, I32, VP, VP, VP, VP, VP]),
     "fdu_rk_step": (I32, [VP, VP, VP, D, VP, VP]),
     "fdu_kernel_times": (I32, [VP, VP, VP, I32, VP, VP]),
-    "fdu_kernel_timer_start": (I32, [VP, I32]),
+    "fdu_kernel_timer_start": (I32, [VP, I32, I32]),
     "fdu_vertex_block_info": (I32, [VP, P(I32), P(I64), P(I32)]),
     "fdu_check_state": (I32, [VP, VP, P(I64), P(I64), VP]),
     "fdu_kernel_timer_stop": (I32, [VP, VP, VP]),
@@ -347,10 +347,14 @@ class Solver:
         _call("fdu_vertex_block_info", self.handle, C.byref(n), C.byref(rows), C.byref(mx))
         return dict(n_blocks=n.value, halo_rows=rows.value, rows_max=mx.value)
 
-    def kernel_timer_start(self, capacity: int = 4096):
-        """Bracket every later kernel launch of this solver with HIP events
-        (first `capacity` launches of each kind) on the launching stream."""
-        _call("fdu_kernel_timer_start", self.handle, int(capacity))
+    PHASES = ("ghost", "edge", "vertex", "cfl")
+
+    def kernel_timer_start(self, capacity: int = 4096, phases=PHASES):
+        """Bracket every later kernel launch of the given kinds by this solver
+        with HIP events (first `capacity` launches of each kind) on the
+        launching stream."""
+        mask = sum(1 << self.PHASES.index(p) for p in phases)
+        _call("fdu_kernel_timer_start", self.handle, int(capacity), int(mask))
 
     def kernel_timer_stop(self):
         """Stop the live timer; returns ({kind: mean ms}, {kind: launches})."""

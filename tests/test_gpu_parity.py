@@ -126,10 +126,21 @@ def test_edge_fluxes(vortex33_p5, sod24_p5):
 
 
 def test_cfl_dt(vortex33_p3, sod24_p5):
+    """The one-launch CFL reduction equals the oracle's, and stays right over
+    repeated calls on changing states (its arrival counter is reset by the
+    last block of every launch)."""
     for c in (vortex33_p3, sod24_p5):
         dt = c.s.cfl_dt(c.w_dev(), 0.5).item()
         ref = c.o.cfl_dt(torch.from_numpy(c.w0), 0.5)
         assert abs(dt - ref) <= 1e-14 * ref
+        d = torch.empty(1, dtype=torch.float64, device="cuda")
+        for rep, scale in enumerate((1.0, 0.5, 2.0, 1.0, 0.25)):
+            w = c.w0.copy()
+            w[:, 1:3] *= scale                       # momentum scaled: another wave speed
+            w[:, 3] = w[:, 3] + 0.5 * (scale ** 2 - 1.0) * (c.w0[:, 1] ** 2 + c.w0[:, 2] ** 2) / c.w0[:, 0]
+            c.s.cfl_dt(c.w_dev(w), 0.3 + 0.1 * rep, d)
+            ref = c.o.cfl_dt(torch.from_numpy(w), 0.3 + 0.1 * rep)
+            assert abs(d.item() - ref) <= 1e-14 * ref, (rep, d.item(), ref)
 
 
 def test_rk3_ten_steps_config1(vortex33_p3):
@@ -203,18 +214,27 @@ def test_errors_are_status_codes():
     del w
 
 
+@pytest.fixture(scope="module")
+def sod1025_prep():
+    fdu = _fdu()
+    m = make_mesh(1025, L=1.0, periodic=False, seed=0, ghost_layers=4)
+    return m, fdu.Prep(m, deg=5, reorder=2)
+
+
 @pytest.mark.slow
-def test_full_size_sod_sampled():
-    """1025^2 rotated Sod (1.05M real vertices) in the bench's launch shape: one
+@pytest.mark.parametrize("edge,vertex", [(1, 10), (2, 12), (1, 14), (2, 15), (1, 3)])
+def test_full_size_sod_sampled(sod1025_prep, edge, vertex):
+    """1025^2 rotated Sod (1.05M real vertices) in the bench's launch shape
+    (Hilbert order, the kernel variants its autotuner chooses between): one
     SSP-RK3 step from the initial state on the GPU; then the residual of the
     stepped state and the first stage of a second step are compared with the
     oracle at sampled vertices (near the interface, at random, walls, corners)."""
     fdu = _fdu()
-    m = make_mesh(1025, L=1.0, periodic=False, seed=0, ghost_layers=4)
-    prep = fdu.Prep(m, deg=5, reorder=1)
+    m, prep = sod1025_prep
     perm = prep.arrays()["perm"]
     s = fdu.Solver(prep, device=0)
-    w0 = torch.from_numpy(sod_state(m)[perm]).cuda()
+    s.set_variants(edge, vertex)
+    w0 = torch.from_numpy(np.ascontiguousarray(sod_state(m)[perm])).cuda()
     w1, w2, w3 = (torch.empty_like(w0) for _ in range(3))
     dt = torch.empty(1, dtype=torch.float64, device="cuda")
     s.cfl_dt(w0, 0.2, dt)
@@ -239,7 +259,7 @@ def test_full_size_sod_sampled():
     o = Oracle(m, deg=5, vertices=sample)
     Ro = o.residual(torch.from_numpy(w_in)).numpy()
     err = rel_err_per_component(R[iperm[sample]], Ro)
-    print("1025^2 sampled residual rel err", err, "sample", len(sample))
+    print("1025^2 sampled residual rel err", edge, vertex, err, "sample", len(sample))
     assert err.max() <= TOL
     dto = o.cfl_dt(torch.from_numpy(w_in), 0.2)
     assert abs(dt.item() - dto) <= 1e-14 * dto
@@ -249,7 +269,7 @@ def test_full_size_sod_sampled():
     assert err1.max() <= 1e-14
 
 
-@pytest.mark.parametrize("edge,vertex", [(e, v) for e in range(2) for v in range(12)])
+@pytest.mark.parametrize("edge,vertex", [(e, v) for e in range(3) for v in range(16)])
 def test_kernel_variants(vortex33_p5, sod24_p5, edge, vertex):
     """Every kernel variant computes the same residual (to the parity bar)."""
     for c in (vortex33_p5, sod24_p5):
@@ -300,9 +320,14 @@ def test_live_kernel_timer(sod24_p5):
     c.s.rk_step(w_b, scr_b, dt_b, cfl=0.2)          # timer off again: nothing recorded, no error
     with pytest.raises(fdu.FduError, match="INVALID_ARG"):
         c.s.kernel_timer_stop()
+    c.s.kernel_timer_start(capacity=16, phases=("edge", "vertex"))
+    c.s.rk_step(w_b, scr_b, dt_b, cfl=0.2)
+    avg, cnt = c.s.kernel_timer_stop()
+    assert cnt == dict(ghost=0, edge=3, vertex=3, cfl=0), cnt
+    assert avg["ghost"] == 0.0 and avg["cfl"] == 0.0 and avg["vertex"] > 0.0
 
 
-@pytest.mark.parametrize("vertex", [0, 3, 10, 11])
+@pytest.mark.parametrize("vertex", [0, 3, 10, 11, 12, 13, 14, 15])
 def test_hilbert_order_variants(vertex):
     """Hilbert vertex order (compact vertex blocks for the LDS-staged variants):
     residual and one RK stage against the oracle, walled and periodic meshes."""
@@ -312,7 +337,30 @@ def test_hilbert_order_variants(vertex):
         assert err.max() <= TOL, err.max()
 
 
-@pytest.mark.parametrize("vertex", [0, 3, 10])
+def test_block_variants_match_the_lds_variant():
+    """Variants 14 and 15 (pointers and own rows also staged in LDS, the stage
+    combine spread over 4 lanes) evaluate the same terms in the same order as
+    variant 10: residual and all three stage types agree bit for bit."""
+    for c in (Case(33, True, 0, 5, "vortex", reorder=2), Case(20, False, 4, 5, "sod", reorder=2)):
+        outs = {}
+        for v in (10, 14, 15):
+            c.s.set_variants(1, v)
+            w = c.w_dev()
+            R = c.s.residual(w)
+            dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+            st = []
+            for k in range(3):
+                out = torch.empty_like(w)
+                c.s.rk_stage(k, w, w, out, dt)
+                st.append(out[:c.m.nv_real].clone())
+            outs[v] = (R, st)
+        for v in (14, 15):
+            assert torch.equal(outs[v][0], outs[10][0]), v
+            for k in range(3):
+                assert torch.equal(outs[v][1][k], outs[10][1][k]), (v, k)
+
+
+@pytest.mark.parametrize("vertex", [0, 3, 10, 14])
 def test_artificial_edges_residual_and_stage(vertex):
     """Degree-3 one-level stencils completed with artificial edges (Sec. 2.2.2):
     residual and one RK stage against the oracle built the same way."""
