@@ -456,6 +456,11 @@ FDU_HD void edge_flux_one(const double W[6][4], const double g[6], const Scheme&
   riemann_flux<double>(wl, wr, nx, ny, S, out);
 }
 
+// Vertex blocks of the LDS-staged vertex kernels: at most kBlockVertices
+// consecutive vertices and kBlockRows staged rows (32 bytes each) per block.
+constexpr int kBlockVertices = 256;
+constexpr int kBlockRows = 768;
+
 // Map a hardware block index to a logical one so that each of the 8 XCDs
 // (blocks are dealt to XCDs round robin) works on one contiguous range.
 __device__ __forceinline__ int xcd_block(int b, int nb) {
@@ -1368,28 +1373,72 @@ __device__ __forceinline__ void vertex_block2(int bk, double* lds, const T* __re
   const int o0 = own[bk];
   const int lane = threadIdx.x % LPV, sub = threadIdx.x / LPV;
   int* lp = reinterpret_cast<int*>(lds + 4 * (na + ne));   // vptr[v0 .. v0 + nb], then eptr[v0 .. v0 + nb]
-  for (int i = threadIdx.x; i < na; i += blockDim.x) {
-    double q[4];
-    load4(w, uv[a0 + i], q);
-    double2* d = reinterpret_cast<double2*>(lds + 4 * i);
-    d[0] = make_double2(q[0], q[1]);
-    d[1] = make_double2(q[2], q[3]);
+  // The first round's stream loads (pointers read from global memory here),
+  // then every thread's share of the staged rows (at most RPT each) loaded
+  // together before any is written to LDS: one memory round trip, not one per
+  // row.
+  BlockFetch<TW, MV, ME> F;
+  {
+    int ptr[4] = {0, 0, 0, 0};
+    if (sub < nb) {
+      ptr[0] = vptr[v0 + sub]; ptr[1] = vptr[v0 + sub + 1];
+      ptr[2] = eptr[v0 + sub]; ptr[3] = eptr[v0 + sub + 1];
+    }
+    F.i = sub;
+    F.pb = ptr[0]; F.pe = ptr[1]; F.qb = ptr[2]; F.qe = ptr[3];
+#pragma unroll
+    for (int s = 0; s < MV; ++s) {
+      const int p = F.pb + lane + s * LPV;
+      F.jv[s] = p < F.pe ? (int)lvcol[p] : -1;
+      F.wf[s] = p < F.pe ? (double)wfg[2 * (size_t)p] : 0.0;
+      F.wg[s] = p < F.pe ? (double)wfg[2 * (size_t)p + 1] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < ME; ++s) {
+      const int p = F.qb + lane + s * LPV;
+      F.ke[s] = p < F.qe ? (int)lecol[p] : -1;
+      F.cw[s] = p < F.qe ? (double)we[p] : 0.0;
+    }
   }
-  for (int i = threadIdx.x; i < ne; i += blockDim.x) {
-    const double2* sp = reinterpret_cast<const double2*>(r + 4 * (size_t)ue[e0 + i]);
-    double2* d = reinterpret_cast<double2*>(lds + 4 * (na + i));
-    d[0] = sp[0];
-    d[1] = sp[1];
-  }
-  for (int i = threadIdx.x; i <= nb; i += blockDim.x) {
-    lp[i] = vptr[v0 + i];
-    lp[nb + 1 + i] = eptr[v0 + i];
+  {
+    constexpr int RPT = (kBlockRows + 255) / 256;   // rows per thread
+    int src[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      src[k] = i < na ? uv[a0 + i] : (i < na + ne ? ue[e0 + i - na] : -1);
+    }
+    double q[RPT][4];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < na) {
+        load4(w, src[k], q[k]);
+      } else if (i < na + ne) {
+        const double2* sp = reinterpret_cast<const double2*>(r + 4 * (size_t)src[k]);
+        const double2 x = sp[0], y = sp[1];
+        q[k][0] = x.x; q[k][1] = x.y; q[k][2] = y.x; q[k][3] = y.y;
+      }
+    }
+    // pointer table entries threadIdx.x and (nb = 256 only) 256
+    int pv = 0, pe = 0, pv2 = 0, pe2 = 0;
+    if ((int)threadIdx.x <= nb) { pv = vptr[v0 + threadIdx.x]; pe = eptr[v0 + threadIdx.x]; }
+    if (threadIdx.x == 0 && nb >= 256) { pv2 = vptr[v0 + 256]; pe2 = eptr[v0 + 256]; }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < na + ne) {
+        double2* d = reinterpret_cast<double2*>(lds + 4 * i);
+        d[0] = make_double2(q[k][0], q[k][1]);
+        d[1] = make_double2(q[k][2], q[k][3]);
+      }
+    }
+    if ((int)threadIdx.x <= nb) { lp[threadIdx.x] = pv; lp[nb + 1 + threadIdx.x] = pe; }
+    if (threadIdx.x == 0 && nb >= 256) { lp[256] = pv2; lp[nb + 257] = pe2; }
   }
   __syncthreads();
   const double* Lv = lds;
   const double* Le = lds + 4 * na;
-  BlockFetch<TW, MV, ME> F;
-  block_fetch<TW, LPV, MV, ME>(F, sub, nb, lane, lp, lvcol, wfg, lecol, we);
   for (int ib = 0; ib < nb; ib += VPR) {
     if (PF == 2) {
       BlockFetch<TW, MV, ME> G;

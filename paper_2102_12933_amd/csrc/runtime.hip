@@ -182,8 +182,6 @@ void fill_ghosts_t(fdu_solver* s, T* w, hipStream_t st) {
   launch_check();
 }
 
-constexpr int kBlockVertices = 256;   // vertex blocks: at most this many vertices
-constexpr int kBlockRows = 768;       // and this many staged rows (24 KB of LDS)
 constexpr int kEdgeVariants = 3;
 constexpr int kVertexVariants = 16;
 
@@ -243,6 +241,9 @@ template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE>
 void vertex_blk_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
                        double a, double b, const double* dt, hipStream_t st) {
   if (s->n_vblocks == 0) return;
+  // the kernel stages at most 3 rows per thread and one pointer pair per thread (+1)
+  if (s->vb_rows_max > kBlockRows || kBlockVertices > 256)
+    throw Error(FDU_ERR_UNSUPPORTED, "vertex blocks exceed the staging capacity of vertex variants 14-15");
   const size_t lds = (size_t)s->vb_rows_max * 4 * sizeof(double) + 2 * (kBlockVertices + 1) * sizeof(int);
   hipLaunchKernelGGL((k_vertex_blk<T, TW, LPV, MV, ME, PF, WPE>), dim3(s->n_vblocks), dim3(256), lds, st, w,
                      s->vblk.p, s->vb_own.p, s->vb_uvp.p, s->vb_uv.p, s->vb_uep.p, s->vb_ue.p, s->vptr.p,
@@ -638,7 +639,8 @@ void batch_stage_vm(fdu_batch* b, int k, hipStream_t st) {
   if (t2 > 0) {
     if (VM == 3)
       hipLaunchKernelGGL((k_batch_vertex_lds<8, 3, 6, 5>), dim3(t2), dim3(256),
-                         (size_t)b->lds_rows * 4 * sizeof(double), st, b->dinst.p, n, b->tb.p, b->S, k, kRK[k][0],
+                         (size_t)b->lds_rows * 4 * sizeof(double) + 2 * (kBlockVertices + 1) * sizeof(int), st,
+                         b->dinst.p, n, b->tb.p, b->S, k, kRK[k][0],
                          kRK[k][1], b->dt.p);
     else
       batch_stage_launch<EV, VM, 2>(b, k, st, (unsigned)t2);
@@ -1150,7 +1152,7 @@ fdu_status fdu_batch_set_states(fdu_batch* b, void* const* w, void* const* scrat
       I.eptr = s->eptr.p; I.ecol = s->ecol.p; I.we = s->we.p; I.cO = s->cO.p; I.hmin = s->hmin.p;
       I.gsrc = s->gsrc.p; I.grefl = reinterpret_cast<const signed char*>(s->grefl.p); I.flux = s->flux.p;
       I.gstate = s->gstate.p;
-      I.vblk = s->vblk.p; I.vb_uvp = s->vb_uvp.p; I.vb_uv = s->vb_uv.p; I.vb_uep = s->vb_uep.p; I.vb_ue = s->vb_ue.p;
+      I.vblk = s->vblk.p; I.vb_own = s->vb_own.p; I.vb_uvp = s->vb_uvp.p; I.vb_uv = s->vb_uv.p; I.vb_uep = s->vb_uep.p; I.vb_ue = s->vb_ue.p;
       I.vb_lvcol = s->vb_lvcol.p; I.vb_lecol = s->vb_lecol.p;
       I.w = (double*)w[i];
       I.w1 = (double*)scratch[i];
@@ -1174,6 +1176,10 @@ fdu_status fdu_batch_set_schedule(fdu_batch* b, int schedule, int edges_per_thre
     need(vertex_mode >= 0 && vertex_mode <= 3, "vertex_mode must be 0, 1, 2 or 3");
     if (vertex_mode == 3 && schedule == 0)
       throw Error(FDU_ERR_UNSUPPORTED, "vertex mode 3 (LDS blocks) needs schedule 1 or 2");
+    if (vertex_mode == 3)
+      for (int i = 0; i < b->n; ++i)
+        if (b->inst[i]->vb_rows_max > kBlockRows)
+          throw Error(FDU_ERR_UNSUPPORTED, "vertex blocks exceed the staging capacity of vertex mode 3");
     DeviceGuard dg(b->device);
     b->schedule = schedule;
     b->tl.ept = edges_per_thread;
