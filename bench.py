@@ -300,6 +300,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--variants", type=int, nargs=2, metavar=("EDGE", "VERTEX"), default=None,
+                    help="use these kernel variants instead of autotuning (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 512 MiB buffer 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -331,9 +333,14 @@ def main():
     dt = torch.empty(1, dtype=torch.float64, device="cuda")
 
     solver.fill_ghosts(w0)
-    tune = solver.autotune(w0, reps=args.kernel_reps)
-    log(f"autotune: edge variants {['%.1f us' % (t * 1e3) for t in tune['edge_ms']]} -> {tune['edge']}, "
-        f"vertex variants {['%.1f us' % (t * 1e3) for t in tune['vertex_ms']]} -> {tune['vertex']}")
+    if args.variants is None:
+        tune = solver.autotune(w0, reps=args.kernel_reps)
+        log(f"autotune: edge variants {['%.1f us' % (t * 1e3) for t in tune['edge_ms']]} -> {tune['edge']}, "
+            f"vertex variants {['%.1f us' % (t * 1e3) for t in tune['vertex_ms']]} -> {tune['vertex']}")
+    else:
+        solver.set_variants(*args.variants)
+        tune = dict(edge=args.variants[0], vertex=args.variants[1], edge_ms=[], vertex_ms=[])
+        log(f"variants given: edge {tune['edge']}, vertex {tune['vertex']}")
 
     # the small kernels (ghost fill, CFL reduction) are timed back to back here, outside the timed region
     small = solver.kernel_times(w0, reps=args.kernel_reps)

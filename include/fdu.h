@@ -344,7 +344,7 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
  *           lanes (15: the next round's index and weight loads issued before
  *           the current round is computed).
  * fdu_set_variants / fdu_get_variants select and report them (n_edge, n_vertex:
- * how many exist); a new solver starts with edge 1 and vertex 3.  fdu_autotune times every edge variant and then every vertex
+ * how many exist); a new solver starts with edge 1 and vertex 15.  fdu_autotune times every edge variant and then every vertex
  * variant on the given state with fdu_kernel_times (reps launches each),
  * writes the mean times (ms) to times_ms[0 .. n_edge + n_vertex - 1] and keeps
  * the fastest of each; synchronous; w and scratch as for fdu_kernel_times. */

@@ -32,7 +32,7 @@ FDU_HD void from_char_T(const Frame& F, const double qb[4], double ab[4]) {
 
 // q += L^T o (transpose of to_char at a fixed frame)
 FDU_HD void to_char_T_acc(const Frame& F, double gm1, const double ob[4], double qb[4]) {
-  const double ic = 1.0 / F.c;
+  const double ic = recip<true>(F.c);
   const double b1 = gm1 * ic * ic, b2 = b1 * F.q2;
   const double coreb = 0.5 * ob[0] - ob[1] + 0.5 * ob[3];
   const double xb = 0.5 * (ob[0] - ob[3]) * ic;   // cotangent of (u_n rho - n.m)
@@ -87,7 +87,7 @@ struct FrameBar {
 
 // Frame cotangents of o = to_char(F, q) for fixed q.
 FDU_HD void to_char_frame_T(const Frame& F, double gm1, const double q[4], const double ob[4], FrameBar& Fb) {
-  const double ic = 1.0 / F.c;
+  const double ic = recip<true>(F.c);
   const double b1 = gm1 * ic * ic;
   const double mv = F.u * q[1] + F.v * q[2];
   const double nm = F.nx * q[1] + F.ny * q[2];
@@ -120,12 +120,12 @@ FDU_HD void from_char_frame_T(const Frame& F, const double a[4], const double qb
 // enthalpy (Hsb) and sqrt(rho) (rsb) to the conservative state q.
 // H_s = gamma E / rho - (gamma - 1) (u^2 + v^2) / 2.
 FDU_HD void roe_side_T(const double q[4], double gm1, double usb, double vsb, double Hsb, double rsb, double qb[4]) {
-  const double iq = 1.0 / q[0];
+  const double iq = recip<true>(q[0]);
   const double us = q[1] * iq, vs = q[2] * iq;
   const double gam = gm1 + 1.0;
   usb -= Hsb * gm1 * us;
   vsb -= Hsb * gm1 * vs;
-  qb[0] += -Hsb * gam * q[3] * iq * iq - (usb * us + vsb * vs) * iq + rsb * 0.5 / ::sqrt(q[0]);
+  qb[0] += -Hsb * gam * q[3] * iq * iq - (usb * us + vsb * vs) * iq + rsb * 0.5 * recip<true>(root<true>(q[0]));
   qb[1] += usb * iq;
   qb[2] += vsb * iq;
   qb[3] += Hsb * gam * iq;
@@ -137,14 +137,14 @@ FDU_HD void roe_frame_T(const Frame& F, const double a[4], const double b[4], do
   // derived fields: u_n, u_t, c, q2 -> (u, v, H)
   double Ub = Fb.u + Fb.un * F.nx - Fb.ut * F.ny;
   double Vb = Fb.v + Fb.un * F.ny + Fb.ut * F.nx;
-  const double t = Fb.c * 0.5 * gm1 / F.c;       // c = sqrt(gm1 (H - q2))
+  const double t = Fb.c * 0.5 * gm1 * recip<true>(F.c);   // c = sqrt(gm1 (H - q2))
   const double Hb = Fb.H + t;
   const double q2b = Fb.q2 - t;
   Ub += q2b * F.u;
   Vb += q2b * F.v;
   // (u, v, H) = (ra x_a + rb x_b) / (ra + rb)
-  const double ra = ::sqrt(a[0]), rb = ::sqrt(b[0]), is = 1.0 / (ra + rb);
-  const double ia = 1.0 / a[0], ib = 1.0 / b[0];
+  const double ra = root<true>(a[0]), rb = root<true>(b[0]), is = recip<true>(ra + rb);
+  const double ia = recip<true>(a[0]), ib = recip<true>(b[0]);
   const double ua = a[1] * ia, va = a[2] * ia, ubs = b[1] * ib, vbs = b[2] * ib;
   const double Ha = (gm1 + 1.0) * a[3] * ia - 0.5 * gm1 * (ua * ua + va * va);
   const double Hbs = (gm1 + 1.0) * b[3] * ib - 0.5 * gm1 * (ubs * ubs + vbs * vbs);
@@ -159,7 +159,7 @@ FDU_HD void roe_frame_T(const Frame& F, const double a[4], const double b[4], do
 // u_n and pb on the pressure.
 FDU_HD void normal_flux_T(const double q[4], double nx, double ny, double gm1, const double Fb[4], double unb,
                           double pb, double qb[4]) {
-  const double ir = 1.0 / q[0];
+  const double ir = recip<true>(q[0]);
   const double u = q[1] * ir, v = q[2] * ir;
   const double p = gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * v));
   const double un = u * nx + v * ny;
@@ -185,7 +185,7 @@ FDU_HD void riemann_flux_T(const double wl[4], const double wr[4], double nx, do
     double Fl[4], Fr[4], unl, unr, c2l, c2r;
     normal_flux<double>(wl, nx, ny, S.gm1, Fl, unl, c2l);
     normal_flux<double>(wr, nx, ny, S.gm1, Fr, unr, c2r);
-    const double cl = ::sqrt(c2l), cr = ::sqrt(c2r);
+    const double cl = root<true>(c2l), cr = root<true>(c2r);
     const double sl = ::fabs(unl) + cl, sr = ::fabs(unr) + cr;
     const bool left = sl >= sr;
     const double sm = left ? sl : sr;
@@ -200,9 +200,9 @@ FDU_HD void riemann_flux_T(const double wl[4], const double wr[4], double nx, do
     const double* q = left ? wl : wr;
     const double un = left ? unl : unr, c = left ? cl : cr, c2 = left ? c2l : c2r;
     const double zero[4] = {0.0, 0.0, 0.0, 0.0};
-    const double c2b = smb * 0.5 / c;
-    double qb[4] = {-c2b * c2 / q[0], 0.0, 0.0, 0.0};
-    normal_flux_T(q, nx, ny, S.gm1, zero, smb * (un < 0.0 ? -1.0 : 1.0), c2b * (S.gm1 + 1.0) / q[0], qb);
+    const double c2b = smb * 0.5 * recip<true>(c);
+    double qb[4] = {-c2b * c2 * recip<true>(q[0]), 0.0, 0.0, 0.0};
+    normal_flux_T(q, nx, ny, S.gm1, zero, smb * (un < 0.0 ? -1.0 : 1.0), c2b * (S.gm1 + 1.0) * recip<true>(q[0]), qb);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if (left) wlb[k] += qb[k]; else wrb[k] += qb[k];
@@ -212,7 +212,7 @@ FDU_HD void riemann_flux_T(const double wl[4], const double wr[4], double nx, do
     return;
   }
   // Roe with Harten's fix: dissipation = from_char(F, h * to_char(F, wr - wl))
-  const Frame F = roe_frame<double>(wl, wr, nx, ny, S.gm1);
+  const Frame F = roe_frame<double, true>(wl, wr, nx, ny, S.gm1);
   double dq[4], a[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) dq[k] = wr[k] - wl[k];
@@ -240,8 +240,8 @@ FDU_HD void riemann_flux_T(const double wl[4], const double wr[4], double nx, do
     const double l = lam[k];
     double lb;
     if (::fabs(l) < delta) {         // h = (l^2 + delta^2) / (2 delta)
-      lb = hk * l / delta;
-      deltab += hk * (delta * delta - l * l) / (2.0 * delta * delta);
+      lb = hk * l * recip<true>(delta);
+      deltab += hk * (delta * delta - l * l) * recip<true>(2.0 * delta * delta);
     } else {                         // h = |l|
       lb = l < 0.0 ? -hk : hk;
     }
@@ -277,7 +277,7 @@ FDU_HD void edge_vjp_one(Load&& load, const double g[6], const double ob[4], con
   double W2[4], W3[4];
   load(2, W2, false);
   load(3, W3, false);
-  const Frame F = roe_frame<double>(W2, W3, nx, ny, S.gm1);
+  const Frame F = roe_frame<double, true>(W2, W3, nx, ny, S.gm1);
   double Cv[6][4];
 #pragma unroll
   for (int k = 0; k < 6; ++k) {

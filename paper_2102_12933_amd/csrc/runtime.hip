@@ -79,7 +79,6 @@ struct fdu_solver {
   // vertex blocks with their stencil halos (LDS-staged vertex variants)
   DevBuf<int32_t> vblk, vb_own, vb_uvp, vb_uv, vb_uep, vb_ue;
   DevBuf<uint16_t> vb_lvcol, vb_lecol;
-  DevBuf<uint32_t> cfl_ticket;   // arrival counter of the one-launch CFL reduction (0 between launches)
   int n_vblocks = 0, vb_rows_max = 0;
   // live kernel timer (fdu_kernel_timer_start/stop): event pairs recorded
   // around each launch of the ghost, edge, vertex and CFL kernels
@@ -92,7 +91,7 @@ struct fdu_solver {
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
   }
   int edge_variant = 1;    // 0: k_edge_flux, 1-2: k_edge_flux_lean (2: held to 4 waves per SIMD)
-  int vertex_variant = 3;  // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair,
+  int vertex_variant = 15; // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair,
                            // 10-13: k_vertex_lds (12-13: blocks walked in reverse), 14-15: k_vertex_blk
 };
 
@@ -298,8 +297,10 @@ void vertex_t(fdu_solver* s, const T* w, int mode, T* R, const T* wn, T* out, do
 template <class T>
 void cfl_t(fdu_solver* s, const T* w, double cfl, double* dt, hipStream_t st) {
   timed_launch(s, 3, st, [&] {
-    hipLaunchKernelGGL(k_cfl<T>, dim3(s->cfl_blocks), dim3(256), 0, st, w, s->hmin.p, (int)s->nv_real,
-                       s->params.gamma, cfl, s->part.p, s->cfl_ticket.p, dt);
+    hipLaunchKernelGGL(k_cfl_partial<T>, dim3(s->cfl_blocks), dim3(256), 0, st, w, s->hmin.p, (int)s->nv_real,
+                       s->params.gamma, s->part.p);
+    launch_check();
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, st, s->part.p, s->cfl_blocks, cfl, dt);
   });
   launch_check();
 }
@@ -897,8 +898,6 @@ fdu_status fdu_finalize(fdu_solver* s) {
     s->h_cO = c;
     s->cfl_blocks = (int)std::min<int64_t>(1024, (s->nv_real + 255) / 256);
     s->part.alloc(s->cfl_blocks);
-    const uint32_t zero = 0;
-    s->cfl_ticket.upload(&zero, 1);
     s->chk.alloc(2);
     build_vertex_blocks(s);
     s->finalized = true;

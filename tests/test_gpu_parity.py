@@ -126,9 +126,8 @@ def test_edge_fluxes(vortex33_p5, sod24_p5):
 
 
 def test_cfl_dt(vortex33_p3, sod24_p5):
-    """The one-launch CFL reduction equals the oracle's, and stays right over
-    repeated calls on changing states (its arrival counter is reset by the
-    last block of every launch)."""
+    """The device CFL reduction equals the oracle's, also over repeated calls
+    on changing states and CFL numbers."""
     for c in (vortex33_p3, sod24_p5):
         dt = c.s.cfl_dt(c.w_dev(), 0.5).item()
         ref = c.o.cfl_dt(torch.from_numpy(c.w0), 0.5)
