@@ -1,8 +1,8 @@
 """Mesh geometry for the oracle: adjacency, minimum-image vectors, the 1D
 curvilinear six-point stencil of every edge and its arc-length coordinates.
 
-Paper: Sec. 2.3.1 (a string of connected edges "as smooth as possible" through
-each edge; Catmull-Rom curves that leave the middle edge tangentially; WENO
+Paper: Sec. 2.3.1 (through each edge, a chain of connected edges chosen to be
+the smoothest available; Catmull-Rom curves that leave the middle edge tangentially; WENO
 along the curve-length coordinate).
 
 Readings of what the paper leaves open:

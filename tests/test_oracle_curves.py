@@ -1,5 +1,5 @@
 """Accuracy of midpoint interpolation along curves (Sec. 2.3.3): fifth order
-when a fixed smooth curve is refined, about first order when a Catmull-Rom
+when a fixed smooth curve is refined, near first order when a Catmull-Rom
 curve stencil is scaled down (the reason the scheme degrades on general
 unstructured meshes, Sec. 3.1)."""
 import os

@@ -139,7 +139,7 @@ def _order(hs, errs):
 
 def test_sin_perturbed_stencils_order():
     """Sec. 2.3.2: sin x, five points moved randomly by up to 50% of the spacing:
-    NU-WENO5 keeps fifth order, standard WENO5 drops to about first order."""
+    NU-WENO5 keeps fifth order, standard WENO5 drops to near first order."""
     hs = 2.0 ** -np.arange(2, 7)
     rng = np.random.default_rng(9)
     nu_err, u_err = [], []
