@@ -325,7 +325,8 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
  * (the parity tests run each one); they differ in schedule and register use:
  *   edge:   0 = coefficient-form WENO, IEEE divisions; 1 = divided-difference
  *           WENO, one side's geometry live at a time, refined reciprocals;
- *           2 = variant 1 with its registers held to 4 waves per SIMD;
+ *           2 = variant 1 held to 4 waves per SIMD (no spills), the characteristic
+ *           frame recomputed for the back projection instead of kept live;
  *   vertex: 0 = 16 lanes per vertex, strided loops; 1, 2, 3 = 16, 32, 8 lanes
  *           per vertex, all index/weight loads issued before all gathers;
  *           4, 5 = strided loops with 8 and 4 lanes per vertex; 6, 7 = strided
@@ -344,7 +345,7 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
  *           lanes (15: the next round's index and weight loads issued before
  *           the current round is computed).
  * fdu_set_variants / fdu_get_variants select and report them (n_edge, n_vertex:
- * how many exist); a new solver starts with edge 1 and vertex 15.  fdu_autotune times every edge variant and then every vertex
+ * how many exist); a new solver starts with edge 2 and vertex 15.  fdu_autotune times every edge variant and then every vertex
  * variant on the given state with fdu_kernel_times (reps launches each),
  * writes the mean times (ms) to times_ms[0 .. n_edge + n_vertex - 1] and keeps
  * the fastest of each; synchronous; w and scratch as for fdu_kernel_times. */

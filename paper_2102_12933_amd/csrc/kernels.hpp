@@ -693,7 +693,9 @@ __device__ __forceinline__ double weno_dd_eval(const WenoDD& G, const double u[5
 
 // Edge flux, register-lean variant: one side's WENO geometry live at a time,
 // divided-difference interpolants, refined reciprocals and square roots.
-template <class T, class TG, int POW>
+// RF: recompute the characteristic frame for the back projection (from
+// reloaded end states) instead of keeping it in registers through the WENO.
+template <class T, class TG, int POW, bool RF>
 __device__ __forceinline__ void edge_lean_body(const T* __restrict__ w, const int* __restrict__ sten,
                                                const TG* __restrict__ geo, double* __restrict__ r, int e,
                                                const Scheme& S) {
@@ -753,6 +755,13 @@ __device__ __forceinline__ void edge_lean_body(const T* __restrict__ w, const in
       wl[k] = cl[k];
       wr[k] = cr[k];
     }
+  } else if (RF) {
+    double a[4], b[4];
+    load4(w, opaque(id[2]), a);
+    load4(w, opaque(id[3]), b);
+    const Frame F2 = roe_frame<double, true>(a, b, nx, ny, S.gm1);
+    from_char(F2, cl, wl);
+    from_char(F2, cr, wr);
   } else {
     from_char(F, cl, wl);
     from_char(F, cr, wr);
@@ -771,14 +780,14 @@ __device__ __forceinline__ void edge_lean_body(const T* __restrict__ w, const in
 
 // The WENO power is uniform over a launch: one branch instead of a select per
 // smoothness indicator.
-template <class T, class TG>
+template <class T, class TG, bool RF = false>
 __device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const int* __restrict__ sten,
                                                const TG* __restrict__ geo, double* __restrict__ r, int e,
                                                const Scheme& S) {
   if (S.power == 2)
-    edge_lean_body<T, TG, 2>(w, sten, geo, r, e, S);
+    edge_lean_body<T, TG, 2, RF>(w, sten, geo, r, e, S);
   else
-    edge_lean_body<T, TG, 1>(w, sten, geo, r, e, S);
+    edge_lean_body<T, TG, 1, RF>(w, sten, geo, r, e, S);
 }
 
 // WPE: waves per SIMD the register allocation is held to (1: unconstrained).
@@ -787,7 +796,7 @@ __global__ void __launch_bounds__(256, WPE) k_edge_flux_lean(const T* __restrict
                                                              const TG* __restrict__ geo, double* __restrict__ r,
                                                              int ne, Scheme S) {
   const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (e < ne) edge_lean_item<T, TG>(w, sten, geo, r, e, S);
+  if (e < ne) edge_lean_item<T, TG, (WPE >= 4)>(w, sten, geo, r, e, S);
 }
 
 // Vertex step, software-pipelined: every lane first loads the ids and weights

@@ -174,7 +174,7 @@ def test_rk_stage_matches_oracle_stage(sod24_p5):
 
 @pytest.mark.parametrize("params", [dict(weno_power=2), dict(riemann=1), dict(positivity=0), dict(interpolation=1),
                                     dict(uniform_weno=1), dict(interpolation=1, uniform_weno=1)])
-@pytest.mark.parametrize("edge", [0, 1])
+@pytest.mark.parametrize("edge", [0, 1, 2])
 def test_parameter_switches(params, edge):
     c = Case(20, True, 0, 5, "vortex", **params)
     c.s.set_variants(edge, 10)
