@@ -299,7 +299,8 @@ fdu_status fdu_kernel_timer_stop(fdu_solver* s, double* avg_ms, int* counts);
  *   tile = passes x 256 / lanes; 3: one tile per vertex block of the
  *   instance with its stencil halo staged in LDS, schedules 1 and 2 only,
  *   FDU_ERR_UNSUPPORTED with 0).  Results equal the plain path's with vertex
- *   variant 0, 4, 3 and 10 respectively, bit for bit.
+ *   variant 0, 4, 3 and 10 respectively, bit for bit (the edge phase runs edge
+ *   variant 0's code when the instances use edge variant 0, else variant 2's).
  * fdu_batch_step: one SSP-RK3 step of every instance with its own dt =
  *   cfl * min hmin/(|u|+c) (computed on the device), asynchronous on stream.
  * fdu_batch_capture: records nsteps steps on stream (not the default stream)
