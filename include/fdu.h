@@ -101,8 +101,8 @@ void fdu_default_params(fdu_params* out);
  *     continues the previous segment's direction, cosines within 1e-12 tie to
  *     the smaller input id) and its Catmull-Rom arc-length coordinates
  *     (Sec. 2.3.1), normalised by the edge length;
- *   - the vertex order (natural, or reverse Cuthill-McKee of the real
- *     vertices) and the flux-edge order (by smallest new end id).
+ *   - the vertex order (natural, reverse Cuthill-McKee or Hilbert order of
+ *     the real vertices) and the flux-edge order (by smallest new end id).
  * Inputs (host, read only during the call):
  *   xy [nv_total][2] double; edges [ne][2] int32 (a < b); tris [nt][3] int32;
  *   ghost_src [ng] int32 (source real vertex of ghost nv_real+i),

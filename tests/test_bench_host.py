@@ -1,0 +1,66 @@
+"""Host-side logic of bench.py (CPU): the one-GPU refusal, the algorithmic byte
+counts behind the roofline, and the lookup of measured HBM traffic, which must
+only be used while the committed counter summary matches the kernel sources."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+
+
+def test_kernel_bytes_counts_every_datum_once():
+    A = dict(nv_total=120, nv_real=100, ne_flux=330, nnz_v=1900, nnz_e=4400)
+    nb = bench.kernel_bytes(A)
+    # edge: ids (24 B) + geometry (48 B) + flux out (32 B) per flux edge, every state row once
+    assert nb["edge"] == 330 * (24 + 48 + 32) + 120 * 32
+    # vertex: pointers, c_O, w_n, out per real vertex; id + 2 weights per vertex entry,
+    # id + weight per edge entry; state rows and flux rows once
+    assert nb["vertex"] == 100 * (8 + 16 + 32 + 32) + 1900 * (4 + 16) + 4400 * (4 + 8) + 120 * 32 + 330 * 32
+    blocks = dict(n_blocks=7, halo_rows=900, rows_max=300)
+    nl = bench.kernel_bytes(A, blocks=blocks)
+    # block variants: 16-bit local ids, plus per block 3 pointers and its row lists
+    assert nl["vertex"] == nb["vertex"] - (1900 + 4400) * 2 + 7 * 12 + 900 * 4
+    assert nl["edge"] == nb["edge"]
+    # FP32 storage halves the state rows and weights, never the FP64 flux rows
+    n4 = bench.kernel_bytes(A, precision_bytes=4)
+    assert n4["edge"] == 330 * (24 + 24 + 32) + 120 * 16
+
+
+def test_every_variant_names_a_kernel():
+    assert set(bench.EDGE_KERNELS) == {0, 1, 2}
+    assert set(bench.VERTEX_KERNELS) == set(range(16))
+    assert all(k.startswith("k_") for k in list(bench.EDGE_KERNELS.values()) + list(bench.VERTEX_KERNELS.values()))
+
+
+def test_traffic_lookup_follows_the_source_hash(tmp_path, monkeypatch):
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    with open(path) as fh:
+        d = json.load(fh)
+    kernel = next(iter(d["kernels"]))
+    if d["source_hash"] == bench.source_hash():
+        assert bench.traffic_from_profiles(kernel, d["N"], d["reorder"]) == d["kernels"][kernel]["bytes_per_launch"]
+    # another workload size or vertex order never borrows the measurement
+    assert bench.traffic_from_profiles(kernel, d["N"] + 1, d["reorder"]) is None
+    assert bench.traffic_from_profiles(kernel, d["N"], (d["reorder"] + 1) % 3) is None
+    # a summary taken on other sources is ignored
+    fake_root = tmp_path
+    (fake_root / "profiles").mkdir()
+    d2 = dict(d, source_hash="0" * 16)
+    (fake_root / "profiles" / "hbm_traffic.json").write_text(json.dumps(d2))
+    monkeypatch.setattr(bench, "ROOT", str(fake_root))
+    monkeypatch.setattr(bench, "source_hash", lambda: "f" * 16)
+    assert bench.traffic_from_profiles(kernel, d["N"], d["reorder"]) is None
+
