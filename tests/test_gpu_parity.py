@@ -194,6 +194,33 @@ def test_natural_order_and_smallest_meshes():
         assert err.max() <= TOL, (N, per, err)
 
 
+def test_compute_calls_reject_bad_arguments(sod24_p5):
+    """Every compute call validates on the host before launching: variant and
+    stage ranges, aliasing that would let a kernel read what another block
+    writes, non-positive CFL, NULL pointers; the solver stays usable."""
+    fdu = _fdu()
+    c = sod24_p5
+    w = c.w_dev()
+    dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+    info = c.s.variants()
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        c.s.set_variants(info["n_edge"], 0)
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        c.s.set_variants(0, info["n_vertex"])
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        c.s.rk_stage(3, w, w, torch.empty_like(w), dt)
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        c.s.rk_stage(1, w, w, w, dt)                       # output aliases the gathered input
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        c.s.cfl_dt(w, 0.0, dt)
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        fdu._call("fdu_residual", c.s.handle, None, None, None)
+    with pytest.raises(ValueError):
+        c.s.residual(w[:-1])                               # wrong shape stops in the binding
+    c.s.set_variants(0, 0)
+    assert _residual_err(c).max() <= TOL
+
+
 def test_bitwise_reproducible(vortex33_p5):
     c = vortex33_p5
     a = c.s.residual(c.w_dev()).cpu()
