@@ -403,6 +403,24 @@ def test_block_variants_match_the_lds_variant():
                 assert torch.equal(outs[v][1][k], outs[10][1][k]), (v, k)
 
 
+def test_block_variants_on_one_level_stencils():
+    """Degree-3 stencils (mostly one-level) give larger vertex blocks (~120
+    vertices instead of ~90): the block variants still equal the LDS variant
+    bit for bit and the oracle to the parity bar."""
+    c = Case(65, True, 0, 3, "vortex", reorder=2)
+    info = c.s.vertex_block_info()
+    assert info["n_blocks"] < c.m.nv_real // 100, info
+    ref = None
+    for v in (10, 14, 15):
+        c.s.set_variants(1, v)
+        err = _residual_err(c)
+        assert err.max() <= TOL, (v, err)
+        R = c.s.residual(c.w_dev())
+        if ref is None:
+            ref = R
+        assert torch.equal(R, ref), v
+
+
 @pytest.mark.parametrize("vertex", [0, 3, 10, 14])
 def test_artificial_edges_residual_and_stage(vertex):
     """Degree-3 one-level stencils completed with artificial edges (Sec. 2.2.2):
