@@ -418,7 +418,8 @@ def main():
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=names[dom], variant=tune[dom], avg_ms=round(kt[dom], 5), launches=kcount[dom],
-                    algorithmic_bytes=nb[dom], timing="timing-only HIP events around every edge-flux and vertex launch in the timed region",
+                    algorithmic_bytes=nb[dom],
+                    timing="timing-only HIP events around every edge-flux and vertex launch in the timed region",
                     copy_gbs=copy_gbs)
     nv_real = A["nv_real"]
     value = nv_real * 3 * args.steps / el
