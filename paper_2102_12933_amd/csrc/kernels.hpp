@@ -1263,30 +1263,42 @@ struct BlockFetch {
   double wf[MV], wg[MV], cw[ME];
 };
 
+// The stream loads of one round.  Slots past a vertex's entry range load
+// entry pb instead (always in range) and are skipped where they are used:
+// loads under a branch make the compiler wait for every load in flight at the
+// join, which would serialise the round's memory requests.
+template <class TW, int LPV, int MV, int ME>
+__device__ __forceinline__ void block_fetch_slots(BlockFetch<TW, MV, ME>& F, int lane,
+                                                  const unsigned short* __restrict__ lvcol,
+                                                  const TW* __restrict__ wfg, const unsigned short* __restrict__ lecol,
+                                                  const TW* __restrict__ we) {
+#pragma unroll
+  for (int s = 0; s < MV; ++s) {
+    const int p = F.pb + lane + s * LPV;
+    const size_t pc = p < F.pe ? p : F.pb;
+    F.jv[s] = (int)lvcol[pc];
+    F.wf[s] = (double)wfg[2 * pc];
+    F.wg[s] = (double)wfg[2 * pc + 1];
+  }
+#pragma unroll
+  for (int s = 0; s < ME; ++s) {
+    const int p = F.qb + lane + s * LPV;
+    const size_t pc = p < F.qe ? p : F.qb;
+    F.ke[s] = (int)lecol[pc];
+    F.cw[s] = (double)we[pc];
+  }
+}
+
 template <class TW, int LPV, int MV, int ME>
 __device__ __forceinline__ void block_fetch(BlockFetch<TW, MV, ME>& F, int i, int nb, int lane,
                                             const int* __restrict__ lp, const unsigned short* __restrict__ lvcol,
                                             const TW* __restrict__ wfg, const unsigned short* __restrict__ lecol,
                                             const TW* __restrict__ we) {
   F.i = i;
-  F.pb = F.pe = F.qb = F.qe = 0;
-  if (i < nb) {
-    F.pb = lp[i]; F.pe = lp[i + 1];
-    F.qb = lp[nb + 1 + i]; F.qe = lp[nb + 2 + i];
-  }
-#pragma unroll
-  for (int s = 0; s < MV; ++s) {
-    const int p = F.pb + lane + s * LPV;
-    F.jv[s] = p < F.pe ? (int)lvcol[p] : -1;
-    F.wf[s] = p < F.pe ? (double)wfg[2 * (size_t)p] : 0.0;
-    F.wg[s] = p < F.pe ? (double)wfg[2 * (size_t)p + 1] : 0.0;
-  }
-#pragma unroll
-  for (int s = 0; s < ME; ++s) {
-    const int p = F.qb + lane + s * LPV;
-    F.ke[s] = p < F.qe ? (int)lecol[p] : -1;
-    F.cw[s] = p < F.qe ? (double)we[p] : 0.0;
-  }
+  const int ic = i < nb ? i : nb, ic1 = i < nb ? i + 1 : nb;   // past the block: an empty entry range
+  F.pb = lp[ic]; F.pe = lp[ic1];
+  F.qb = lp[nb + 1 + ic]; F.qe = lp[nb + 1 + ic1];
+  block_fetch_slots<TW, LPV, MV, ME>(F, lane, lvcol, wfg, lecol, we);
 }
 
 __device__ __forceinline__ double pick4(const double x[4], int k) {
@@ -1313,7 +1325,7 @@ __device__ __forceinline__ void block_compute(const BlockFetch<TW, MV, ME>& F, i
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int s = 0; s < MV; ++s) {
-    if (F.jv[s] >= 0) {
+    if (F.pb + lane + s * LPV < F.pe) {
       const double2* lp = reinterpret_cast<const double2*>(Lv + 4 * F.jv[s]);
       const double2 x = lp[0], y = lp[1];
       const double q[4] = {x.x, x.y, y.x, y.y};
@@ -1325,7 +1337,7 @@ __device__ __forceinline__ void block_compute(const BlockFetch<TW, MV, ME>& F, i
   }
 #pragma unroll
   for (int s = 0; s < ME; ++s) {
-    if (F.ke[s] >= 0) {
+    if (F.qb + lane + s * LPV < F.qe) {
       const double2* lp = reinterpret_cast<const double2*>(Le + 4 * F.ke[s]);
       const double2 x = lp[0], y = lp[1];
       acc[0] += F.cw[s] * x.x; acc[1] += F.cw[s] * x.y; acc[2] += F.cw[s] * y.x; acc[3] += F.cw[s] * y.y;
@@ -1388,50 +1400,47 @@ __device__ __forceinline__ void vertex_block2(int bk, double* lds, const T* __re
   // row.
   BlockFetch<TW, MV, ME> F;
   {
-    int ptr[4] = {0, 0, 0, 0};
-    if (sub < nb) {
-      ptr[0] = vptr[v0 + sub]; ptr[1] = vptr[v0 + sub + 1];
-      ptr[2] = eptr[v0 + sub]; ptr[3] = eptr[v0 + sub + 1];
-    }
+    const int ic = v0 + (sub < nb ? sub : nb), ic1 = v0 + (sub < nb ? sub + 1 : nb);   // past the block: empty
     F.i = sub;
-    F.pb = ptr[0]; F.pe = ptr[1]; F.qb = ptr[2]; F.qe = ptr[3];
-#pragma unroll
-    for (int s = 0; s < MV; ++s) {
-      const int p = F.pb + lane + s * LPV;
-      F.jv[s] = p < F.pe ? (int)lvcol[p] : -1;
-      F.wf[s] = p < F.pe ? (double)wfg[2 * (size_t)p] : 0.0;
-      F.wg[s] = p < F.pe ? (double)wfg[2 * (size_t)p + 1] : 0.0;
-    }
-#pragma unroll
-    for (int s = 0; s < ME; ++s) {
-      const int p = F.qb + lane + s * LPV;
-      F.ke[s] = p < F.qe ? (int)lecol[p] : -1;
-      F.cw[s] = p < F.qe ? (double)we[p] : 0.0;
-    }
+    F.pb = vptr[ic]; F.pe = vptr[ic1];
+    F.qb = eptr[ic]; F.qe = eptr[ic1];
+    block_fetch_slots<TW, LPV, MV, ME>(F, lane, lvcol, wfg, lecol, we);
   }
   {
+    // row i of the staging list: state row uv[a0 + i] (i < na) or flux row
+    // ue[e0 + i - na]; threads past the list load row 0 of the state list
+    // (in range) and do not store it
     constexpr int RPT = (kBlockRows + 255) / 256;   // rows per thread
     int src[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int i = threadIdx.x + 256 * k;
-      src[k] = i < na ? uv[a0 + i] : (i < na + ne ? ue[e0 + i - na] : -1);
+      src[k] = i < na ? uv[a0 + i] : (i < na + ne ? ue[e0 + i - na] : uv[a0]);
     }
     double q[RPT][4];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int i = threadIdx.x + 256 * k;
-      if (i < na) {
-        load4(w, src[k], q[k]);
-      } else if (i < na + ne) {
-        const double2* sp = reinterpret_cast<const double2*>(r + 4 * (size_t)src[k]);
+      if constexpr (sizeof(T) == sizeof(double)) {
+        const double* row = (i < na || i >= na + ne) ? reinterpret_cast<const double*>(w) + 4 * (size_t)src[k]
+                                                     : r + 4 * (size_t)src[k];
+        const double2* sp = reinterpret_cast<const double2*>(row);
         const double2 x = sp[0], y = sp[1];
         q[k][0] = x.x; q[k][1] = x.y; q[k][2] = y.x; q[k][3] = y.y;
+      } else {
+        if (i < na) {
+          load4(w, src[k], q[k]);
+        } else if (i < na + ne) {
+          const double2* sp = reinterpret_cast<const double2*>(r + 4 * (size_t)src[k]);
+          const double2 x = sp[0], y = sp[1];
+          q[k][0] = x.x; q[k][1] = x.y; q[k][2] = y.x; q[k][3] = y.y;
+        }
       }
     }
     // pointer table entries threadIdx.x and (nb = 256 only) 256
-    int pv = 0, pe = 0, pv2 = 0, pe2 = 0;
-    if ((int)threadIdx.x <= nb) { pv = vptr[v0 + threadIdx.x]; pe = eptr[v0 + threadIdx.x]; }
+    const int t0 = (int)threadIdx.x <= nb ? (int)threadIdx.x : nb;
+    const int pv = vptr[v0 + t0], pe = eptr[v0 + t0];
+    int pv2 = 0, pe2 = 0;
     if (threadIdx.x == 0 && nb >= 256) { pv2 = vptr[v0 + 256]; pe2 = eptr[v0 + 256]; }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
