@@ -300,7 +300,7 @@ fdu_status fdu_kernel_timer_stop(fdu_solver* s, double* avg_ms, int* counts);
  *   instance with its stencil halo staged in LDS, schedules 1 and 2 only,
  *   FDU_ERR_UNSUPPORTED with 0).  Results equal the plain path's with vertex
  *   variant 0, 4, 3 and 10 respectively, bit for bit (the edge phase runs edge
- *   variant 0's code when the instances use edge variant 0, else variant 2's).
+ *   variant 0's code when the instances use edge variant 0, else variant 1's).
  * fdu_batch_step: one SSP-RK3 step of every instance with its own dt =
  *   cfl * min hmin/(|u|+c) (computed on the device), asynchronous on stream.
  * fdu_batch_capture: records nsteps steps on stream (not the default stream)
@@ -346,7 +346,7 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
  *           lanes (15: the next round's index and weight loads issued before
  *           the current round is computed).
  * fdu_set_variants / fdu_get_variants select and report them (n_edge, n_vertex:
- * how many exist); a new solver starts with edge 2 and vertex 15.  fdu_autotune times every edge variant and then every vertex
+ * how many exist); a new solver starts with edge 1 and vertex 15.  fdu_autotune times every edge variant and then every vertex
  * variant on the given state with fdu_kernel_times (reps launches each),
  * writes the mean times (ms) to times_ms[0 .. n_edge + n_vertex - 1] and keeps
  * the fastest of each; synchronous; w and scratch as for fdu_kernel_times. */

@@ -94,7 +94,7 @@ struct VertexMode {
 // PH < 0: fused schedule with dynamic tickets and dependency waits; PH 0/1/2:
 // a kernel holding only that phase's code, one tile per block (no waits).
 template <int EV, int VM, int PH>
-__global__ void __launch_bounds__(256, PH == 1 ? 4 : 1) k_batch_stage(const BatchInst* __restrict__ inst, int n,
+__global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict__ inst, int n,
                                                      const int* __restrict__ tb, int total, unsigned* ctr, Scheme S,
                                                      int k, double a, double b, const double* __restrict__ dt,
                                                      int* err, BatchTiling tl) {
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256, PH == 1 ? 4 : 1) k_batch_stage(const Batc
         const int e = (local * tl.ept + q) * 256 + threadIdx.x;
         if (e < I.ne) {
           if (EV == 1)
-            edge_lean_item<double, double, true>(wprev, I.sten, I.geo, I.flux, e, S);
+            edge_lean_item<double, double>(wprev, I.sten, I.geo, I.flux, e, S);
           else
             edge_item<double, double>(wprev, I.sten, I.geo, I.flux, e, S);
         }

@@ -705,25 +705,20 @@ __device__ __forceinline__ void edge_lean_body(const T* __restrict__ w, const in
     int2 a = sp[0], b = sp[1], c = sp[2];
     id[0] = a.x; id[1] = a.y; id[2] = b.x; id[3] = b.y; id[4] = c.x; id[5] = c.y;
   }
-  double W2[4], W3[4];
-  load4(w, id[2], W2);
-  load4(w, id[3], W3);
+  // all six states and the geometry are requested before any is used (a use
+  // between two loads would make the compiler wait for the first)
+  double Cv[6][4];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) load4(w, id[k], Cv[k]);
   double g[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = (double)geo[6 * (size_t)e + k];
   const double nx = g[4], ny = g[5];
-  const Frame F = roe_frame<double, true>(W2, W3, nx, ny, S.gm1);
-  double Cv[6][4];
+  const Frame F = roe_frame<double, true>(Cv[2], Cv[3], nx, ny, S.gm1);
+  if (!S.conservative) {
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    double q[4];
-    if (k == 2) { for (int i = 0; i < 4; ++i) q[i] = W2[i]; }
-    else if (k == 3) { for (int i = 0; i < 4; ++i) q[i] = W3[i]; }
-    else load4(w, id[k], q);
-    if (S.conservative) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Cv[k][i] = q[i];
-    } else {
+    for (int k = 0; k < 6; ++k) {
+      const double q[4] = {Cv[k][0], Cv[k][1], Cv[k][2], Cv[k][3]};
       to_char<double, true>(F, S.gm1, q, Cv[k]);
     }
   }

@@ -90,7 +90,7 @@ struct fdu_solver {
     for (auto& v : timer_ev)
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
   }
-  int edge_variant = 2;    // 0: k_edge_flux, 1-2: k_edge_flux_lean (2: held to 4 waves per SIMD)
+  int edge_variant = 1;    // 0: k_edge_flux, 1-2: k_edge_flux_lean (2: held to 4 waves per SIMD)
   int vertex_variant = 15; // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair,
                            // 10-13: k_vertex_lds (12-13: blocks walked in reverse), 14-15: k_vertex_blk
 };

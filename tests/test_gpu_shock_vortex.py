@@ -91,7 +91,7 @@ def test_dirichlet_batch_equals_plain(schedule, vmode):
     inst = [channel(seed=k, center=(2.0 + k, 0.5 * k), mv=0.6 + 0.2 * k) for k in range(3)]
     ref = []
     for m, w0, gs, perm, s in inst:
-        s.set_variants(2, {0: 0, 2: 3, 3: 10}[vmode])   # the batch's lean edge phase is edge variant 2
+        s.set_variants(1, {0: 0, 2: 3, 3: 10}[vmode])   # the batch's lean edge phase is edge variant 1
         w = torch.from_numpy(np.ascontiguousarray(w0[perm])).cuda()
         scr = torch.empty(2 * m.nv, 4, dtype=torch.float64, device="cuda")
         dt = torch.empty(1, dtype=torch.float64, device="cuda")
