@@ -446,12 +446,33 @@ __global__ void __launch_bounds__(256) k_edge_cot(const int* __restrict__ tptr, 
   const bool active = k < ne;
   double a[4] = {0.0, 0.0, 0.0, 0.0};
   if (active) {
-    for (int p = tptr[k] + lane; p < tptr[k + 1]; p += LPV) {
-      double q[4];
-      load4(Rbar, trow[p], q);
-      const double c = (double)tw[p];
+    // the first NS entries of each lane: indices, weights and rows requested
+    // together (slots past the list read entry 0 and are not used), then the
+    // rest one by one; the per-lane order of the sum is the list order
+    constexpr int NS = 2;
+    const int pb = tptr[k], pe = tptr[k + 1];
+    int row[NS];
+    double c[NS], q[NS][4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] -= c * q[i];
+    for (int s = 0; s < NS; ++s) {
+      const int p = pb + lane + s * LPV;
+      const int pc = p < pe ? p : 0;
+      row[s] = trow[pc];
+      c[s] = (double)tw[pc];
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) load4(Rbar, row[s], q[s]);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (pb + lane + s * LPV < pe)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] -= c[s] * q[s][i];
+    for (int p = pb + lane + NS * LPV; p < pe; p += LPV) {
+      double qq[4];
+      load4(Rbar, trow[p], qq);
+      const double cc = (double)tw[p];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] -= cc * qq[i];
     }
   }
 #pragma unroll
@@ -504,20 +525,56 @@ __global__ void __launch_bounds__(256) k_vertex_vjp(const T* __restrict__ w, con
   const bool active = v < nv;
   double fb[4] = {0.0, 0.0, 0.0, 0.0}, gb[4] = {0.0, 0.0, 0.0, 0.0}, sl[4] = {0.0, 0.0, 0.0, 0.0};
   if (active) {
-    for (int p = tptr[v] + lane; p < tptr[v + 1]; p += LPV) {
-      double q[4];
-      load4(Rbar, trow[p], q);
-      const double a = (double)twfg[2 * (size_t)p], b = (double)twfg[2 * (size_t)p + 1];
+    // as in k_edge_cot: the first NS entries of each lane's share of both
+    // lists requested together, the rest one by one, list order per lane
+    constexpr int NS = 3;
+    const int pb = tptr[v], pe = tptr[v + 1], qb = sptr[v], qe = sptr[v + 1];
+    int row[NS], col[NS];
+    double a[NS], b[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int p = pb + lane + s * LPV, pc = p < pe ? p : 0;
+      row[s] = trow[pc];
+      a[s] = (double)twfg[2 * (size_t)pc];
+      b[s] = (double)twfg[2 * (size_t)pc + 1];
+      const int r = qb + lane + s * LPV;
+      col[s] = scol[r < qe ? r : 0];
+    }
+    double q[NS][4], x[NS][4];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      load4(Rbar, row[s], q[s]);
+      const double2* sp = reinterpret_cast<const double2*>(slots + 4 * (size_t)col[s]);
+      const double2 x0 = sp[0], x1 = sp[1];
+      x[s][0] = x0.x; x[s][1] = x0.y; x[s][2] = x1.x; x[s][3] = x1.y;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (pb + lane + s * LPV < pe)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          fb[i] -= a[s] * q[s][i];
+          gb[i] -= b[s] * q[s][i];
+        }
+    for (int p = pb + lane + NS * LPV; p < pe; p += LPV) {
+      double qq[4];
+      load4(Rbar, trow[p], qq);
+      const double aa = (double)twfg[2 * (size_t)p], bb = (double)twfg[2 * (size_t)p + 1];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        fb[i] -= a * q[i];
-        gb[i] -= b * q[i];
+        fb[i] -= aa * qq[i];
+        gb[i] -= bb * qq[i];
       }
     }
-    for (int p = sptr[v] + lane; p < sptr[v + 1]; p += LPV) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (qb + lane + s * LPV < qe) {
+        sl[0] += x[s][0]; sl[1] += x[s][1]; sl[2] += x[s][2]; sl[3] += x[s][3];
+      }
+    for (int p = qb + lane + NS * LPV; p < qe; p += LPV) {
       const double2* sp = reinterpret_cast<const double2*>(slots + 4 * (size_t)scol[p]);
-      const double2 x = sp[0], y = sp[1];
-      sl[0] += x.x; sl[1] += x.y; sl[2] += y.x; sl[3] += y.y;
+      const double2 x0 = sp[0], x1 = sp[1];
+      sl[0] += x0.x; sl[1] += x0.y; sl[2] += x1.x; sl[3] += x1.y;
     }
   }
 #pragma unroll
