@@ -808,32 +808,34 @@ __device__ __forceinline__ void vertex_pipe_item(const T* __restrict__ w, const 
                                                  int lane) {
   const bool active = v < nreal;
   const int vv = active ? v : 0;
-  int vb = 0, ve = 0, eb = 0, ee = 0;
-  if (active) {
-    vb = vptr[v]; ve = vptr[v + 1];
-    eb = eptr[v]; ee = eptr[v + 1];
-  }
+  // every load issued unconditionally at an in-range index (an idle thread
+  // reads an empty range at row nreal, a slot past its range reads entry 0);
+  // the predicates are applied where the values are used
+  const int vc = active ? v : nreal, vc1 = active ? v + 1 : nreal;
+  const int vb = vptr[vc], ve = vptr[vc1], eb = eptr[vc], ee = eptr[vc1];
   int jv[MV], ke[ME];
   double wf[MV], wg[MV], cw[ME];
 #pragma unroll
   for (int s = 0; s < MV; ++s) {
     const int p = vb + lane + s * LPV;
-    jv[s] = p < ve ? vcol[p] : -1;
-    wf[s] = p < ve ? (double)wfg[2 * (size_t)p] : 0.0;
-    wg[s] = p < ve ? (double)wfg[2 * (size_t)p + 1] : 0.0;
+    const size_t pc = p < ve ? p : 0;
+    jv[s] = vcol[pc];
+    wf[s] = (double)wfg[2 * pc];
+    wg[s] = (double)wfg[2 * pc + 1];
   }
 #pragma unroll
   for (int s = 0; s < ME; ++s) {
     const int p = eb + lane + s * LPV;
-    ke[s] = p < ee ? ecol[p] : -1;
-    cw[s] = p < ee ? (double)we[p] : 0.0;
+    const size_t pc = p < ee ? p : 0;
+    ke[s] = ecol[pc];
+    cw[s] = (double)we[pc];
   }
   double qv[MV][4], rv[ME][4];
 #pragma unroll
-  for (int s = 0; s < MV; ++s) load4(w, jv[s] >= 0 ? jv[s] : vv, qv[s]);
+  for (int s = 0; s < MV; ++s) load4(w, vb + lane + s * LPV < ve ? jv[s] : vv, qv[s]);
 #pragma unroll
   for (int s = 0; s < ME; ++s) {
-    const double2* rp = reinterpret_cast<const double2*>(r + 4 * (size_t)(ke[s] >= 0 ? ke[s] : 0));
+    const double2* rp = reinterpret_cast<const double2*>(r + 4 * (size_t)(eb + lane + s * LPV < ee ? ke[s] : 0));
     const double2 x = rp[0], y = rp[1];
     rv[s][0] = x.x; rv[s][1] = x.y; rv[s][2] = y.x; rv[s][3] = y.y;
   }
@@ -843,7 +845,7 @@ __device__ __forceinline__ void vertex_pipe_item(const T* __restrict__ w, const 
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int s = 0; s < MV; ++s) {
-    if (jv[s] >= 0) {
+    if (vb + lane + s * LPV < ve) {
       double f[4], g[4];
       euler_fg(qv[s], gm1, f, g);
 #pragma unroll
@@ -851,9 +853,11 @@ __device__ __forceinline__ void vertex_pipe_item(const T* __restrict__ w, const 
     }
   }
 #pragma unroll
-  for (int s = 0; s < ME; ++s)
+  for (int s = 0; s < ME; ++s) {
+    const double c = eb + lane + s * LPV < ee ? cw[s] : 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] += cw[s] * rv[s][k];
+    for (int k = 0; k < 4; ++k) acc[k] += c * rv[s][k];
+  }
   // tails (rare: stencils larger than the pipelined slots)
   for (int p = vb + lane + MV * LPV; p < ve; p += LPV) {
     const int j = vcol[p];
@@ -1077,24 +1081,26 @@ __device__ __forceinline__ void vertex_fetch(VertexFetch<TW, MV, ME>& F, int v, 
                                              const int* __restrict__ vptr, const unsigned short* __restrict__ lvcol,
                                              const TW* __restrict__ wfg, const int* __restrict__ eptr,
                                              const unsigned short* __restrict__ lecol, const TW* __restrict__ we) {
+  // unconditional loads at in-range indices (past the block: an empty range;
+  // past a range: entry 0), the predicates applied where the values are used
   F.v = v;
-  F.pb = F.pe = F.qb = F.qe = 0;
-  if (v < v1) {
-    F.pb = vptr[v]; F.pe = vptr[v + 1];
-    F.qb = eptr[v]; F.qe = eptr[v + 1];
-  }
+  const int vc = v < v1 ? v : v1, vc1 = v < v1 ? v + 1 : v1;
+  F.pb = vptr[vc]; F.pe = vptr[vc1];
+  F.qb = eptr[vc]; F.qe = eptr[vc1];
 #pragma unroll
   for (int s = 0; s < MV; ++s) {
     const int p = F.pb + lane + s * LPV;
-    F.jv[s] = p < F.pe ? (int)lvcol[p] : -1;
-    F.wf[s] = p < F.pe ? (double)wfg[2 * (size_t)p] : 0.0;
-    F.wg[s] = p < F.pe ? (double)wfg[2 * (size_t)p + 1] : 0.0;
+    const size_t pc = p < F.pe ? p : 0;
+    F.jv[s] = (int)lvcol[pc];
+    F.wf[s] = (double)wfg[2 * pc];
+    F.wg[s] = (double)wfg[2 * pc + 1];
   }
 #pragma unroll
   for (int s = 0; s < ME; ++s) {
     const int p = F.qb + lane + s * LPV;
-    F.ke[s] = p < F.qe ? (int)lecol[p] : -1;
-    F.cw[s] = p < F.qe ? (double)we[p] : 0.0;
+    const size_t pc = p < F.qe ? p : 0;
+    F.ke[s] = (int)lecol[pc];
+    F.cw[s] = (double)we[pc];
   }
 }
 
@@ -1116,7 +1122,7 @@ __device__ __forceinline__ void vertex_lds_compute(const VertexFetch<TW, MV, ME>
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int s = 0; s < MV; ++s) {
-    if (F.jv[s] >= 0) {
+    if (F.pb + lane + s * LPV < F.pe) {
       const double2* lp = reinterpret_cast<const double2*>(Lv + 4 * F.jv[s]);
       const double2 x = lp[0], y = lp[1];
       const double q[4] = {x.x, x.y, y.x, y.y};
@@ -1128,7 +1134,7 @@ __device__ __forceinline__ void vertex_lds_compute(const VertexFetch<TW, MV, ME>
   }
 #pragma unroll
   for (int s = 0; s < ME; ++s) {
-    if (F.ke[s] >= 0) {
+    if (F.qb + lane + s * LPV < F.qe) {
       const double2* lp = reinterpret_cast<const double2*>(Le + 4 * F.ke[s]);
       const double2 x = lp[0], y = lp[1];
       acc[0] += F.cw[s] * x.x; acc[1] += F.cw[s] * x.y; acc[2] += F.cw[s] * y.x; acc[3] += F.cw[s] * y.y;
