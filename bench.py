@@ -34,7 +34,7 @@ SOD_CFL = 0.2
 METRIC = "vertex-stage updates/sec + HBM GB/s vs peak; batched & adjoint vs plain path"
 
 
-def kernel_bytes(A, precision_bytes=8, blocks=None):
+def kernel_bytes(A, precision_bytes=8, blocks=None, packed=None):
     """Algorithmic bytes per launch (each datum counted once).
     edge:   per flux edge 6 int32 ids + 6 geometry values + 4 flux values written,
             plus every state row read once;
@@ -43,15 +43,37 @@ def kernel_bytes(A, precision_bytes=8, blocks=None):
             1 weight, plus every state row and every flux row read once.
             LDS-staged variants (blocks given): 16-bit ids instead, plus per block
             3 int32 pointers and its int32 row lists (the row data itself still
-            counted once)."""
+            counted once).  Packed-id variants (packed = the number of vertex and
+            edge entries past each vertex's first round): the first-round ids
+            are one 12-byte record per vertex and lane (96 bytes per real
+            vertex), only the entries past the first round keep 16-bit ids."""
     s = precision_bytes
     nvt, nvr, nef, nzv, nze = A["nv_total"], A["nv_real"], A["ne_flux"], A["nnz_v"], A["nnz_e"]
     edge = nef * (6 * 4 + 6 * s + 4 * 8) + nvt * 4 * s
     ids = 4 if blocks is None else 2
-    vertex = nvr * (2 * 4 + 2 * 8 + 4 * s + 4 * s) + nzv * (ids + 2 * s) + nze * (ids + s) + nvt * 4 * s + nef * 4 * 8
+    vertex = nvr * (2 * 4 + 2 * 8 + 4 * s + 4 * s) + nzv * 2 * s + nze * s + nvt * 4 * s + nef * 4 * 8
+    if packed is None:
+        vertex += (nzv + nze) * ids
+    else:
+        vertex += nvr * 8 * 12 + (packed[0] + packed[1]) * 2
     if blocks is not None:
         vertex += blocks["n_blocks"] * 3 * 4 + blocks["halo_rows"] * 4
     return dict(edge=edge, vertex=vertex)
+
+
+# vertex variants whose first-round ids are packed, and the entries a first round covers
+PACKED_VERTEX_VARIANTS = (16, 17)
+PACKED_ROUND = (24, 48)
+
+
+def entries_past_first_round(A):
+    """Vertex and edge entries that a packed-id variant reads with 16-bit ids
+    (those past the first 24 vertex and 48 edge entries of each real vertex)."""
+    import numpy as np
+
+    nv = np.diff(np.asarray(A["vptr"], dtype=np.int64)[: A["nv_real"] + 1])
+    ne = np.diff(np.asarray(A["eptr"], dtype=np.int64)[: A["nv_real"] + 1])
+    return int(np.maximum(nv - PACKED_ROUND[0], 0).sum()), int(np.maximum(ne - PACKED_ROUND[1], 0).sum())
 
 
 # kernel (template instance) behind each variant number of the library
@@ -64,7 +86,10 @@ VERTEX_KERNELS = {0: "k_vertex<double, double, 16, false>", 1: "k_vertex_pipe<do
                   8: "k_vertex_pair<double, double, 16, 3, 6>", 9: "k_vertex_pair<double, double, 8, 5, 11>",
                   10: "k_vertex_lds<double, double, 8, 3, 6, 1, 5>", 11: "k_vertex_lds<double, double, 4, 5, 11, 1, 4>",
                   12: "k_vertex_lds<double, double, 8, 3, 6, 1, 5>", 13: "k_vertex_lds<double, double, 4, 5, 11, 1, 4>",
-                  14: "k_vertex_blk<double, double, 8, 3, 6, 1, 5>", 15: "k_vertex_blk<double, double, 8, 3, 6, 2, 4>"}
+                  14: "k_vertex_blk<double, double, 8, 3, 6, 1, 5, false>",
+                  15: "k_vertex_blk<double, double, 8, 3, 6, 2, 4, false>",
+                  16: "k_vertex_blk<double, double, 8, 3, 6, 1, 5, true>",
+                  17: "k_vertex_blk<double, double, 8, 3, 6, 2, 4, true>"}
 KERNEL_SOURCES = ("csrc/kernels.hpp", "csrc/batch.hpp", "csrc/adjoint.hpp", "csrc/runtime.hip", "build.py")
 
 
@@ -391,7 +416,8 @@ def main():
         del g
 
     blocks = solver.vertex_block_info() if tune["vertex"] >= 10 else None
-    nb = kernel_bytes(A, blocks=blocks)
+    packed = entries_past_first_round(A) if tune["vertex"] in PACKED_VERTEX_VARIANTS else None
+    nb = kernel_bytes(A, blocks=blocks, packed=packed)
     kern = {}
     for k in ("edge", "vertex"):
         ms = kt[k]

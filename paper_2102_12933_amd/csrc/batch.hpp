@@ -170,9 +170,10 @@ __global__ void __launch_bounds__(256, WPE) k_batch_vertex_lds(const BatchInst* 
   const BatchInst& I = inst[j];
   const double* wprev = k == 0 ? I.w : (k == 1 ? I.w1 : I.w2);
   double* wout = k == 0 ? I.w1 : (k == 1 ? I.w2 : I.w);
-  vertex_block2<double, double, LPV, MV, ME, 1>(t - tb[2 * n + j], lds, wprev, I.vblk, I.vb_own, I.vb_uvp, I.vb_uv,
-                                                I.vb_uep, I.vb_ue, I.vptr, I.vb_lvcol, I.wfg, I.eptr, I.vb_lecol,
-                                                I.we, I.cO, I.flux, S.gm1, 1, nullptr, I.w, wout, a, b, dt + j);
+  vertex_block2<double, double, LPV, MV, ME, 1, false>(t - tb[2 * n + j], lds, wprev, I.vblk, I.vb_own, I.vb_uvp,
+                                                       I.vb_uv, I.vb_uep, I.vb_ue, I.vptr, I.vb_lvcol, I.wfg, I.eptr,
+                                                       I.vb_lecol, I.we, I.cO, I.flux, S.gm1, 1, nullptr, I.w, wout, a,
+                                                       b, dt + j, nullptr);
 }
 
 // Per-instance CFL: block minima of hmin_v / (|u_v| + c_v) over 256-vertex

@@ -461,6 +461,18 @@ FDU_HD void edge_flux_one(const double W[6][4], const double g[6], const Scheme&
 constexpr int kBlockVertices = 256;
 constexpr int kBlockRows = 768;
 
+// Packed stream ids of the block kernel (vertex variants 16-17).  For every
+// real vertex and each of its 8 lanes, one 12-byte record holds the
+// block-local ids of the lane's first-round entries: its 3 state-row slots,
+// then its 6 flux-row slots (entry pb + lane + 8 s of the vertex's range),
+// 10 bits each, three to a 32-bit word; slots past the range hold 0.  One
+// coalesced load per lane replaces nine 16-bit gathers.
+constexpr int kPackLPV = 8, kPackMV = 3, kPackME = 6;
+static_assert(kBlockRows <= 1024, "local ids of a block must fit in 10 bits");
+struct PackedIds {
+  unsigned w[3];
+};
+
 // Map a hardware block index to a logical one so that each of the 8 XCDs
 // (blocks are dealt to XCDs round robin) works on one contiguous range.
 __device__ __forceinline__ int xcd_block(int b, int nb) {
@@ -1268,16 +1280,27 @@ struct BlockFetch {
 // entry pb instead (always in range) and are skipped where they are used:
 // loads under a branch make the compiler wait for every load in flight at the
 // join, which would serialise the round's memory requests.
-template <class TW, int LPV, int MV, int ME>
+// With PK the ids come from the vertex's packed record (vrow: the vertex's
+// row, in range also past the block) instead of the 16-bit id lists.
+template <class TW, int LPV, int MV, int ME, bool PK>
 __device__ __forceinline__ void block_fetch_slots(BlockFetch<TW, MV, ME>& F, int lane,
                                                   const unsigned short* __restrict__ lvcol,
                                                   const TW* __restrict__ wfg, const unsigned short* __restrict__ lecol,
-                                                  const TW* __restrict__ we) {
+                                                  const TW* __restrict__ we, const PackedIds* __restrict__ pk,
+                                                  int vrow) {
+  if constexpr (PK) {
+    static_assert(LPV == kPackLPV && MV == kPackMV && ME == kPackME, "layout of the packed ids");
+    const PackedIds k = pk[(size_t)vrow * LPV + lane];
+#pragma unroll
+    for (int s = 0; s < MV; ++s) F.jv[s] = (int)((k.w[s / 3] >> (10 * (s % 3))) & 1023u);
+#pragma unroll
+    for (int s = 0; s < ME; ++s) F.ke[s] = (int)((k.w[(MV + s) / 3] >> (10 * ((MV + s) % 3))) & 1023u);
+  }
 #pragma unroll
   for (int s = 0; s < MV; ++s) {
     const int p = F.pb + lane + s * LPV;
     const size_t pc = p < F.pe ? p : F.pb;
-    F.jv[s] = (int)lvcol[pc];
+    if constexpr (!PK) F.jv[s] = (int)lvcol[pc];
     F.wf[s] = (double)wfg[2 * pc];
     F.wg[s] = (double)wfg[2 * pc + 1];
   }
@@ -1285,21 +1308,21 @@ __device__ __forceinline__ void block_fetch_slots(BlockFetch<TW, MV, ME>& F, int
   for (int s = 0; s < ME; ++s) {
     const int p = F.qb + lane + s * LPV;
     const size_t pc = p < F.qe ? p : F.qb;
-    F.ke[s] = (int)lecol[pc];
+    if constexpr (!PK) F.ke[s] = (int)lecol[pc];
     F.cw[s] = (double)we[pc];
   }
 }
 
-template <class TW, int LPV, int MV, int ME>
-__device__ __forceinline__ void block_fetch(BlockFetch<TW, MV, ME>& F, int i, int nb, int lane,
+template <class TW, int LPV, int MV, int ME, bool PK>
+__device__ __forceinline__ void block_fetch(BlockFetch<TW, MV, ME>& F, int i, int v0, int nb, int lane,
                                             const int* __restrict__ lp, const unsigned short* __restrict__ lvcol,
                                             const TW* __restrict__ wfg, const unsigned short* __restrict__ lecol,
-                                            const TW* __restrict__ we) {
+                                            const TW* __restrict__ we, const PackedIds* __restrict__ pk) {
   F.i = i;
   const int ic = i < nb ? i : nb, ic1 = i < nb ? i + 1 : nb;   // past the block: an empty entry range
   F.pb = lp[ic]; F.pe = lp[ic1];
   F.qb = lp[nb + 1 + ic]; F.qe = lp[nb + 1 + ic1];
-  block_fetch_slots<TW, LPV, MV, ME>(F, lane, lvcol, wfg, lecol, we);
+  block_fetch_slots<TW, LPV, MV, ME, PK>(F, lane, lvcol, wfg, lecol, we, pk, v0 + (i < nb ? i : 0));
 }
 
 __device__ __forceinline__ double pick4(const double x[4], int k) {
@@ -1377,7 +1400,7 @@ __device__ __forceinline__ void block_compute(const BlockFetch<TW, MV, ME>& F, i
   }
 }
 
-template <class T, class TW, int LPV, int MV, int ME, int PF>
+template <class T, class TW, int LPV, int MV, int ME, int PF, bool PK>
 __device__ __forceinline__ void vertex_block2(int bk, double* lds, const T* __restrict__ w, const int* __restrict__ blk,
                                               const int* __restrict__ own, const int* __restrict__ uvp,
                                               const int* __restrict__ uv, const int* __restrict__ uep,
@@ -1387,7 +1410,8 @@ __device__ __forceinline__ void vertex_block2(int bk, double* lds, const T* __re
                                               const TW* __restrict__ we, const double* __restrict__ cO,
                                               const double* __restrict__ r, double gm1, int mode,
                                               T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
-                                              double a, double b, const double* __restrict__ dt_dev) {
+                                              double a, double b, const double* __restrict__ dt_dev,
+                                              const PackedIds* __restrict__ pk) {
   constexpr int VPR = 256 / LPV;    // vertices per round
   const int v0 = blk[bk], nb = blk[bk + 1] - v0;
   const int a0 = uvp[bk], na = uvp[bk + 1] - a0;
@@ -1405,7 +1429,7 @@ __device__ __forceinline__ void vertex_block2(int bk, double* lds, const T* __re
     F.i = sub;
     F.pb = vptr[ic]; F.pe = vptr[ic1];
     F.qb = eptr[ic]; F.qe = eptr[ic1];
-    block_fetch_slots<TW, LPV, MV, ME>(F, lane, lvcol, wfg, lecol, we);
+    block_fetch_slots<TW, LPV, MV, ME, PK>(F, lane, lvcol, wfg, lecol, we, pk, v0 + (sub < nb ? sub : 0));
   }
   {
     // row i of the staging list: state row uv[a0 + i] (i < na) or flux row
@@ -1461,19 +1485,19 @@ __device__ __forceinline__ void vertex_block2(int bk, double* lds, const T* __re
   for (int ib = 0; ib < nb; ib += VPR) {
     if (PF == 2) {
       BlockFetch<TW, MV, ME> G;
-      block_fetch<TW, LPV, MV, ME>(G, ib + VPR + sub, nb, lane, lp, lvcol, wfg, lecol, we);
+      block_fetch<TW, LPV, MV, ME, PK>(G, ib + VPR + sub, v0, nb, lane, lp, lvcol, wfg, lecol, we, pk);
       block_compute<T, TW, LPV, MV, ME>(F, v0, nb, o0, lane, Lv, Le, lvcol, wfg, lecol, we, cO, gm1, mode, R, wn, out,
                                         a, b, dt_dev);
       F = G;
     } else {
-      if (ib > 0) block_fetch<TW, LPV, MV, ME>(F, ib + sub, nb, lane, lp, lvcol, wfg, lecol, we);
+      if (ib > 0) block_fetch<TW, LPV, MV, ME, PK>(F, ib + sub, v0, nb, lane, lp, lvcol, wfg, lecol, we, pk);
       block_compute<T, TW, LPV, MV, ME>(F, v0, nb, o0, lane, Lv, Le, lvcol, wfg, lecol, we, cO, gm1, mode, R, wn, out,
                                         a, b, dt_dev);
     }
   }
 }
 
-template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE>
+template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE, bool PK>
 __global__ void __launch_bounds__(256, WPE) k_vertex_blk(const T* __restrict__ w, const int* __restrict__ blk,
                                                          const int* __restrict__ own, const int* __restrict__ uvp,
                                                          const int* __restrict__ uv, const int* __restrict__ uep,
@@ -1485,10 +1509,12 @@ __global__ void __launch_bounds__(256, WPE) k_vertex_blk(const T* __restrict__ w
                                                          const double* __restrict__ r, double gm1, int mode,
                                                          T* __restrict__ R, const T* __restrict__ wn,
                                                          T* __restrict__ out, double a, double b,
-                                                         const double* __restrict__ dt_dev) {
+                                                         const double* __restrict__ dt_dev,
+                                                         const PackedIds* __restrict__ pk) {
   extern __shared__ double lds[];   // [rows][4] state then flux rows, then the block's CSR pointers
-  vertex_block2<T, TW, LPV, MV, ME, PF>(xcd_block(blockIdx.x, gridDim.x), lds, w, blk, own, uvp, uv, uep, ue, vptr,
-                                        lvcol, wfg, eptr, lecol, we, cO, r, gm1, mode, R, wn, out, a, b, dt_dev);
+  vertex_block2<T, TW, LPV, MV, ME, PF, PK>(xcd_block(blockIdx.x, gridDim.x), lds, w, blk, own, uvp, uv, uep, ue,
+                                            vptr, lvcol, wfg, eptr, lecol, we, cO, r, gm1, mode, R, wn, out, a, b,
+                                            dt_dev, pk);
 }
 
 // State check: counts real rows that are not finite or not physical

@@ -79,6 +79,7 @@ struct fdu_solver {
   // vertex blocks with their stencil halos (LDS-staged vertex variants)
   DevBuf<int32_t> vblk, vb_own, vb_uvp, vb_uv, vb_uep, vb_ue;
   DevBuf<uint16_t> vb_lvcol, vb_lecol;
+  DevBuf<PackedIds> vb_pk;   // packed first-round ids per real vertex and lane (vertex variants 16-17)
   int n_vblocks = 0, vb_rows_max = 0;
   // live kernel timer (fdu_kernel_timer_start/stop): event pairs recorded
   // around each launch of the ghost, edge, vertex and CFL kernels
@@ -91,8 +92,9 @@ struct fdu_solver {
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
   }
   int edge_variant = 1;    // 0: k_edge_flux, 1-2: k_edge_flux_lean (2: held to 4 waves per SIMD)
-  int vertex_variant = 15; // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair,
-                           // 10-13: k_vertex_lds (12-13: blocks walked in reverse), 14-15: k_vertex_blk
+  int vertex_variant = 17; // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair,
+                           // 10-13: k_vertex_lds (12-13: blocks walked in reverse), 14-17: k_vertex_blk
+                           // (16-17: packed first-round ids)
 };
 
 namespace {
@@ -182,7 +184,7 @@ void fill_ghosts_t(fdu_solver* s, T* w, hipStream_t st) {
 }
 
 constexpr int kEdgeVariants = 3;
-constexpr int kVertexVariants = 16;
+constexpr int kVertexVariants = 18;
 
 template <class T, class TG>
 void edge_flux_launch(fdu_solver* s, const T* w, const TG* geo, double* r, hipStream_t st) {
@@ -236,18 +238,20 @@ void vertex_lds_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, i
                      s->vb_lecol.p, we, s->cO.p, s->flux.p, s->params.gamma - 1.0, mode, R, wn, out, a, b, dt, rev);
 }
 
-template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE>
+template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE, bool PK>
 void vertex_blk_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
                        double a, double b, const double* dt, hipStream_t st) {
   if (s->n_vblocks == 0) return;
   // the kernel stages at most 3 rows per thread and one pointer pair per thread (+1)
   if (s->vb_rows_max > kBlockRows || kBlockVertices > 256)
-    throw Error(FDU_ERR_UNSUPPORTED, "vertex blocks exceed the staging capacity of vertex variants 14-15");
+    throw Error(FDU_ERR_UNSUPPORTED, "vertex blocks exceed the staging capacity of vertex variants 14-17");
+  if (PK && s->vb_pk.n != (size_t)s->nv_real * kPackLPV)
+    throw Error(FDU_ERR_STATE, "packed vertex-block ids were not built");
   const size_t lds = (size_t)s->vb_rows_max * 4 * sizeof(double) + 2 * (kBlockVertices + 1) * sizeof(int);
-  hipLaunchKernelGGL((k_vertex_blk<T, TW, LPV, MV, ME, PF, WPE>), dim3(s->n_vblocks), dim3(256), lds, st, w,
+  hipLaunchKernelGGL((k_vertex_blk<T, TW, LPV, MV, ME, PF, WPE, PK>), dim3(s->n_vblocks), dim3(256), lds, st, w,
                      s->vblk.p, s->vb_own.p, s->vb_uvp.p, s->vb_uv.p, s->vb_uep.p, s->vb_ue.p, s->vptr.p,
                      s->vb_lvcol.p, wfg, s->eptr.p, s->vb_lecol.p, we, s->cO.p, s->flux.p, s->params.gamma - 1.0, mode,
-                     R, wn, out, a, b, dt);
+                     R, wn, out, a, b, dt, s->vb_pk.p);
 }
 
 template <class T, class TW, int LPV, bool NT>
@@ -276,8 +280,10 @@ void vertex_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int m
     case 11: vertex_lds_launch<T, TW, 4, 5, 11, 1, 4>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
     case 12: vertex_lds_launch<T, TW, 8, 3, 6, 1, 5>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st, 1); break;
     case 13: vertex_lds_launch<T, TW, 4, 5, 11, 1, 4>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st, 1); break;
-    case 14: vertex_blk_launch<T, TW, 8, 3, 6, 1, 5>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 15: vertex_blk_launch<T, TW, 8, 3, 6, 2, 4>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 14: vertex_blk_launch<T, TW, 8, 3, 6, 1, 5, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 15: vertex_blk_launch<T, TW, 8, 3, 6, 2, 4, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 16: vertex_blk_launch<T, TW, 8, 3, 6, 1, 5, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 17: vertex_blk_launch<T, TW, 8, 3, 6, 2, 4, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
     default: vertex_loop_launch<T, TW, 16, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st);
   }
 }
@@ -399,6 +405,26 @@ void build_vertex_blocks(fdu_solver* s) {
   s->vb_lecol.upload(lecol.data(), lecol.size());
   s->n_vblocks = (int)blk.size() - 1;
   s->vb_rows_max = rows_max;
+  // packed first-round ids (10 bits each; built when every block fits the block kernel)
+  if (rows_max <= kBlockRows) {
+    std::vector<PackedIds> pk((size_t)n * kPackLPV);
+    for (int64_t v = 0; v < n; ++v) {
+      for (int l = 0; l < kPackLPV; ++l) {
+        PackedIds& k = pk[(size_t)v * kPackLPV + l];
+        k.w[0] = k.w[1] = k.w[2] = 0u;
+        for (int j = 0; j < kPackMV + kPackME; ++j) {
+          const bool vs = j < kPackMV;
+          const int64_t p = (vs ? s->h_vptr[v] : s->h_eptr[v]) + l + (int64_t)kPackLPV * (vs ? j : j - kPackMV);
+          const int64_t pe = vs ? s->h_vptr[v + 1] : s->h_eptr[v + 1];
+          const unsigned id = p < pe ? (unsigned)(vs ? lvcol[p] : lecol[p]) : 0u;
+          k.w[j / 3] |= id << (10 * (j % 3));
+        }
+      }
+    }
+    s->vb_pk.upload(pk.data(), pk.size());
+  } else {
+    s->vb_pk.release();
+  }
 }
 
 // Transposed maps for the adjoint, built on the host from the uploaded

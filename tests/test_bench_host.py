@@ -34,14 +34,25 @@ def test_kernel_bytes_counts_every_datum_once():
     # block variants: 16-bit local ids, plus per block 3 pointers and its row lists
     assert nl["vertex"] == nb["vertex"] - (1900 + 4400) * 2 + 7 * 12 + 900 * 4
     assert nl["edge"] == nb["edge"]
+    # packed-id variants: a 12-byte record per real vertex and lane for the first
+    # round's ids, 16-bit ids only for the entries past it
+    npk = bench.kernel_bytes(A, blocks=blocks, packed=(5, 7))
+    assert npk["vertex"] == nl["vertex"] - (1900 + 4400) * 2 + 100 * 8 * 12 + (5 + 7) * 2
     # FP32 storage halves the state rows and weights, never the FP64 flux rows
     n4 = bench.kernel_bytes(A, precision_bytes=4)
     assert n4["edge"] == 330 * (24 + 24 + 32) + 120 * 16
 
 
+def test_entries_past_first_round():
+    import numpy as np
+    # three real vertices with 30, 10, 24 vertex entries and 50, 48, 60 edge entries, one ghost
+    A = dict(nv_real=3, vptr=np.array([0, 30, 40, 64, 64]), eptr=np.array([0, 50, 98, 158, 158]))
+    assert bench.entries_past_first_round(A) == (6, 2 + 12)
+
+
 def test_every_variant_names_a_kernel():
     assert set(bench.EDGE_KERNELS) == {0, 1, 2}
-    assert set(bench.VERTEX_KERNELS) == set(range(16))
+    assert set(bench.VERTEX_KERNELS) == set(range(18))
     assert all(k.startswith("k_") for k in list(bench.EDGE_KERNELS.values()) + list(bench.VERTEX_KERNELS.values()))
 
 

@@ -248,7 +248,7 @@ def sod1025_prep():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("edge,vertex", [(1, 10), (2, 12), (1, 14), (2, 15), (1, 3)])
+@pytest.mark.parametrize("edge,vertex", [(1, 10), (2, 12), (1, 14), (2, 15), (1, 16), (2, 17), (1, 3)])
 def test_full_size_sod_sampled(sod1025_prep, edge, vertex):
     """1025^2 rotated Sod (1.05M real vertices) in the bench's launch shape
     (Hilbert order, the kernel variants its autotuner chooses between): one
@@ -295,7 +295,7 @@ def test_full_size_sod_sampled(sod1025_prep, edge, vertex):
     assert err1.max() <= 1e-14
 
 
-@pytest.mark.parametrize("edge,vertex", [(e, v) for e in range(3) for v in range(16)])
+@pytest.mark.parametrize("edge,vertex", [(e, v) for e in range(3) for v in range(18)])
 def test_kernel_variants(vortex33_p5, sod24_p5, edge, vertex):
     """Every kernel variant computes the same residual (to the parity bar)."""
     for c in (vortex33_p5, sod24_p5):
@@ -353,7 +353,7 @@ def test_live_kernel_timer(sod24_p5):
     assert avg["ghost"] == 0.0 and avg["cfl"] == 0.0 and avg["vertex"] > 0.0
 
 
-@pytest.mark.parametrize("vertex", [0, 3, 10, 11, 12, 13, 14, 15])
+@pytest.mark.parametrize("vertex", [0, 3, 10, 11, 12, 13, 14, 15, 16, 17])
 def test_hilbert_order_variants(vertex):
     """Hilbert vertex order (compact vertex blocks for the LDS-staged variants):
     residual and one RK stage against the oracle, walled and periodic meshes."""
@@ -382,11 +382,12 @@ def test_edge_variant_two_matches_variant_one():
 
 def test_block_variants_match_the_lds_variant():
     """Variants 14 and 15 (pointers and own rows also staged in LDS, the stage
-    combine spread over 4 lanes) evaluate the same terms in the same order as
-    variant 10: residual and all three stage types agree bit for bit."""
+    combine spread over 4 lanes) and 16 and 17 (the same with packed first-round
+    ids) evaluate the same terms in the same order as variant 10: residual and
+    all three stage types agree bit for bit."""
     for c in (Case(33, True, 0, 5, "vortex", reorder=2), Case(20, False, 4, 5, "sod", reorder=2)):
         outs = {}
-        for v in (10, 14, 15):
+        for v in (10, 14, 15, 16, 17):
             c.s.set_variants(1, v)
             w = c.w_dev()
             R = c.s.residual(w)
@@ -397,7 +398,7 @@ def test_block_variants_match_the_lds_variant():
                 c.s.rk_stage(k, w, w, out, dt)
                 st.append(out[:c.m.nv_real].clone())
             outs[v] = (R, st)
-        for v in (14, 15):
+        for v in (14, 15, 16, 17):
             assert torch.equal(outs[v][0], outs[10][0]), v
             for k in range(3):
                 assert torch.equal(outs[v][1][k], outs[10][1][k]), (v, k)
@@ -411,7 +412,7 @@ def test_block_variants_on_one_level_stencils():
     info = c.s.vertex_block_info()
     assert info["n_blocks"] < c.m.nv_real // 100, info
     ref = None
-    for v in (10, 14, 15):
+    for v in (10, 14, 15, 16, 17):
         c.s.set_variants(1, v)
         err = _residual_err(c)
         assert err.max() <= TOL, (v, err)
@@ -421,7 +422,7 @@ def test_block_variants_on_one_level_stencils():
         assert torch.equal(R, ref), v
 
 
-@pytest.mark.parametrize("vertex", [0, 3, 10, 14])
+@pytest.mark.parametrize("vertex", [0, 3, 10, 14, 16])
 def test_artificial_edges_residual_and_stage(vertex):
     """Degree-3 one-level stencils completed with artificial edges (Sec. 2.2.2):
     residual and one RK stage against the oracle built the same way."""
