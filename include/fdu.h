@@ -297,9 +297,10 @@ fdu_status fdu_kernel_timer_stop(fdu_solver* s, double* avg_ms, int* counts);
  *   that), vertex_passes and vertex_mode (0: strided loops, 16 lanes per
  *   vertex; 1: strided loops, 8 lanes; 2: pipelined loads, 8 lanes; vertex
  *   tile = passes x 256 / lanes; 3: one tile per vertex block of the
- *   instance with its stencil halo staged in LDS, schedules 1 and 2 only,
- *   FDU_ERR_UNSUPPORTED with 0).  Results equal the plain path's with vertex
- *   variant 0, 4, 3 and 10 respectively, bit for bit (the edge phase runs edge
+ *   instance with its stencil halo staged in LDS, the code of vertex variant
+ *   17, schedules 1 and 2 only, FDU_ERR_UNSUPPORTED with 0).  Results equal
+ *   the plain path's with vertex variant 0, 4, 3 and 10 (= 14-17)
+ *   respectively, bit for bit (the edge phase runs edge
  *   variant 0's code when the instances use edge variant 0, else variant 1's).
  * fdu_batch_step: one SSP-RK3 step of every instance with its own dt =
  *   cfl * min hmin/(|u|+c) (computed on the device), asynchronous on stream.

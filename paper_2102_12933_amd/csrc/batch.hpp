@@ -37,6 +37,7 @@ struct BatchInst {
   const int* vb_ue;
   const unsigned short* vb_lvcol;
   const unsigned short* vb_lecol;
+  const PackedIds* vb_pk;   // packed first-round ids of the block kernel
   double* flux;
   double* w;    // state (in/out)
   double* w1;   // stage buffers
@@ -159,7 +160,8 @@ __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict
 
 // Vertex phase over all instances with the stencil halos staged in LDS: one
 // workgroup per vertex block; tile t of the phase maps to (instance, block).
-template <int LPV, int MV, int ME, int WPE>
+// The block kernel of vertex variant 17 (next round prefetched, packed ids).
+template <int LPV, int MV, int ME, int PF, int WPE, bool PK>
 __global__ void __launch_bounds__(256, WPE) k_batch_vertex_lds(const BatchInst* __restrict__ inst, int n,
                                                                const int* __restrict__ tb, Scheme S, int k, double a,
                                                                double b, const double* __restrict__ dt) {
@@ -170,10 +172,10 @@ __global__ void __launch_bounds__(256, WPE) k_batch_vertex_lds(const BatchInst* 
   const BatchInst& I = inst[j];
   const double* wprev = k == 0 ? I.w : (k == 1 ? I.w1 : I.w2);
   double* wout = k == 0 ? I.w1 : (k == 1 ? I.w2 : I.w);
-  vertex_block2<double, double, LPV, MV, ME, 1, false>(t - tb[2 * n + j], lds, wprev, I.vblk, I.vb_own, I.vb_uvp,
-                                                       I.vb_uv, I.vb_uep, I.vb_ue, I.vptr, I.vb_lvcol, I.wfg, I.eptr,
-                                                       I.vb_lecol, I.we, I.cO, I.flux, S.gm1, 1, nullptr, I.w, wout, a,
-                                                       b, dt + j, nullptr);
+  vertex_block2<double, double, LPV, MV, ME, PF, PK>(t - tb[2 * n + j], lds, wprev, I.vblk, I.vb_own, I.vb_uvp,
+                                                     I.vb_uv, I.vb_uep, I.vb_ue, I.vptr, I.vb_lvcol, I.wfg, I.eptr,
+                                                     I.vb_lecol, I.we, I.cO, I.flux, S.gm1, 1, nullptr, I.w, wout, a, b,
+                                                     dt + j, I.vb_pk);
 }
 
 // Per-instance CFL: block minima of hmin_v / (|u_v| + c_v) over 256-vertex

@@ -665,7 +665,7 @@ void batch_stage_vm(fdu_batch* b, int k, hipStream_t st) {
   if (t1 > 0) batch_stage_launch<EV, VM, 1>(b, k, st, (unsigned)t1);
   if (t2 > 0) {
     if (VM == 3)
-      hipLaunchKernelGGL((k_batch_vertex_lds<8, 3, 6, 5>), dim3(t2), dim3(256),
+      hipLaunchKernelGGL((k_batch_vertex_lds<8, 3, 6, 2, 4, true>), dim3(t2), dim3(256),
                          (size_t)b->lds_rows * 4 * sizeof(double) + 2 * (kBlockVertices + 1) * sizeof(int), st,
                          b->dinst.p, n, b->tb.p, b->S, k, kRK[k][0],
                          kRK[k][1], b->dt.p);
@@ -1178,7 +1178,7 @@ fdu_status fdu_batch_set_states(fdu_batch* b, void* const* w, void* const* scrat
       I.gsrc = s->gsrc.p; I.grefl = reinterpret_cast<const signed char*>(s->grefl.p); I.flux = s->flux.p;
       I.gstate = s->gstate.p;
       I.vblk = s->vblk.p; I.vb_own = s->vb_own.p; I.vb_uvp = s->vb_uvp.p; I.vb_uv = s->vb_uv.p; I.vb_uep = s->vb_uep.p; I.vb_ue = s->vb_ue.p;
-      I.vb_lvcol = s->vb_lvcol.p; I.vb_lecol = s->vb_lecol.p;
+      I.vb_lvcol = s->vb_lvcol.p; I.vb_lecol = s->vb_lecol.p; I.vb_pk = s->vb_pk.p;
       I.w = (double*)w[i];
       I.w1 = (double*)scratch[i];
       I.w2 = (double*)scratch[i] + 4 * s->nv_total;
@@ -1203,7 +1203,8 @@ fdu_status fdu_batch_set_schedule(fdu_batch* b, int schedule, int edges_per_thre
       throw Error(FDU_ERR_UNSUPPORTED, "vertex mode 3 (LDS blocks) needs schedule 1 or 2");
     if (vertex_mode == 3)
       for (int i = 0; i < b->n; ++i)
-        if (b->inst[i]->vb_rows_max > kBlockRows)
+        if (b->inst[i]->vb_rows_max > kBlockRows ||
+            b->inst[i]->vb_pk.n != (size_t)b->inst[i]->nv_real * kPackLPV)
           throw Error(FDU_ERR_UNSUPPORTED, "vertex blocks exceed the staging capacity of vertex mode 3");
     DeviceGuard dg(b->device);
     b->schedule = schedule;
