@@ -348,9 +348,11 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
  *           the current round is computed); 16, 17 = variants 14 and 15 with
  *           each lane's first-round row indices (3 state rows, 6 flux rows)
  *           packed 10 bits each into one 12-byte record per vertex and lane,
- *           built at fdu_finalize: one load instead of nine 16-bit gathers.
+ *           built at fdu_finalize: one load instead of nine 16-bit gathers,
+ *           kept packed until each position is used (variant 16 fits 5 waves
+ *           per SIMD without spilling).
  * fdu_set_variants / fdu_get_variants select and report them (n_edge, n_vertex:
- * how many exist); a new solver starts with edge 1 and vertex 17.  fdu_autotune times every edge variant and then every vertex
+ * how many exist); a new solver starts with edge 1 and vertex 16.  fdu_autotune times every edge variant and then every vertex
  * variant on the given state with fdu_kernel_times (reps launches each),
  * writes the mean times (ms) to times_ms[0 .. n_edge + n_vertex - 1] and keeps
  * the fastest of each; synchronous; w and scratch as for fdu_kernel_times. */

@@ -1269,11 +1269,23 @@ __global__ void __launch_bounds__(256, WPE) k_vertex_lds(const T* __restrict__ w
 // front of them), and the stage combine is done by lanes 0-3 of each vertex,
 // one component each (8-byte loads and stores instead of 32-byte rows).  The
 // arithmetic is that of k_vertex_lds with the same lanes, term for term.
-template <class TW, int MV, int ME>
+// With PK the round's row positions stay in their packed words until used
+// (3 registers instead of 9 while a prefetched round waits).
+template <class TW, int MV, int ME, bool PK>
 struct BlockFetch {
   int i, pb, pe, qb, qe;
-  int jv[MV], ke[ME];
+  int jv[PK ? 1 : MV], ke[PK ? 1 : ME];
+  unsigned pk[PK ? 3 : 1];
   double wf[MV], wg[MV], cw[ME];
+  // row position of vertex slot s and of edge slot s (s known at compile time)
+  __device__ __forceinline__ int vid(int s) const {
+    if constexpr (PK) return (int)((pk[s / 3] >> (10 * (s % 3))) & 1023u);
+    else return jv[s];
+  }
+  __device__ __forceinline__ int eid(int s) const {
+    if constexpr (PK) return (int)((pk[(MV + s) / 3] >> (10 * ((MV + s) % 3))) & 1023u);
+    else return ke[s];
+  }
 };
 
 // The stream loads of one round.  Slots past a vertex's entry range load
@@ -1283,7 +1295,7 @@ struct BlockFetch {
 // With PK the ids come from the vertex's packed record (vrow: the vertex's
 // row, in range also past the block) instead of the 16-bit id lists.
 template <class TW, int LPV, int MV, int ME, bool PK>
-__device__ __forceinline__ void block_fetch_slots(BlockFetch<TW, MV, ME>& F, int lane,
+__device__ __forceinline__ void block_fetch_slots(BlockFetch<TW, MV, ME, PK>& F, int lane,
                                                   const unsigned short* __restrict__ lvcol,
                                                   const TW* __restrict__ wfg, const unsigned short* __restrict__ lecol,
                                                   const TW* __restrict__ we, const PackedIds* __restrict__ pk,
@@ -1291,10 +1303,7 @@ __device__ __forceinline__ void block_fetch_slots(BlockFetch<TW, MV, ME>& F, int
   if constexpr (PK) {
     static_assert(LPV == kPackLPV && MV == kPackMV && ME == kPackME, "layout of the packed ids");
     const PackedIds k = pk[(size_t)vrow * LPV + lane];
-#pragma unroll
-    for (int s = 0; s < MV; ++s) F.jv[s] = (int)((k.w[s / 3] >> (10 * (s % 3))) & 1023u);
-#pragma unroll
-    for (int s = 0; s < ME; ++s) F.ke[s] = (int)((k.w[(MV + s) / 3] >> (10 * ((MV + s) % 3))) & 1023u);
+    F.pk[0] = k.w[0]; F.pk[1] = k.w[1]; F.pk[2] = k.w[2];
   }
 #pragma unroll
   for (int s = 0; s < MV; ++s) {
@@ -1314,7 +1323,7 @@ __device__ __forceinline__ void block_fetch_slots(BlockFetch<TW, MV, ME>& F, int
 }
 
 template <class TW, int LPV, int MV, int ME, bool PK>
-__device__ __forceinline__ void block_fetch(BlockFetch<TW, MV, ME>& F, int i, int v0, int nb, int lane,
+__device__ __forceinline__ void block_fetch(BlockFetch<TW, MV, ME, PK>& F, int i, int v0, int nb, int lane,
                                             const int* __restrict__ lp, const unsigned short* __restrict__ lvcol,
                                             const TW* __restrict__ wfg, const unsigned short* __restrict__ lecol,
                                             const TW* __restrict__ we, const PackedIds* __restrict__ pk) {
@@ -1329,8 +1338,8 @@ __device__ __forceinline__ double pick4(const double x[4], int k) {
   return k == 0 ? x[0] : (k == 1 ? x[1] : (k == 2 ? x[2] : x[3]));
 }
 
-template <class T, class TW, int LPV, int MV, int ME>
-__device__ __forceinline__ void block_compute(const BlockFetch<TW, MV, ME>& F, int v0, int nb, int o0, int lane,
+template <class T, class TW, int LPV, int MV, int ME, bool PK>
+__device__ __forceinline__ void block_compute(const BlockFetch<TW, MV, ME, PK>& F, int v0, int nb, int o0, int lane,
                                               const double* __restrict__ Lv, const double* __restrict__ Le,
                                               const unsigned short* __restrict__ lvcol, const TW* __restrict__ wfg,
                                               const unsigned short* __restrict__ lecol, const TW* __restrict__ we,
@@ -1350,7 +1359,7 @@ __device__ __forceinline__ void block_compute(const BlockFetch<TW, MV, ME>& F, i
 #pragma unroll
   for (int s = 0; s < MV; ++s) {
     if (F.pb + lane + s * LPV < F.pe) {
-      const double2* lp = reinterpret_cast<const double2*>(Lv + 4 * F.jv[s]);
+      const double2* lp = reinterpret_cast<const double2*>(Lv + 4 * F.vid(s));
       const double2 x = lp[0], y = lp[1];
       const double q[4] = {x.x, x.y, y.x, y.y};
       double f[4], g[4];
@@ -1362,7 +1371,7 @@ __device__ __forceinline__ void block_compute(const BlockFetch<TW, MV, ME>& F, i
 #pragma unroll
   for (int s = 0; s < ME; ++s) {
     if (F.qb + lane + s * LPV < F.qe) {
-      const double2* lp = reinterpret_cast<const double2*>(Le + 4 * F.ke[s]);
+      const double2* lp = reinterpret_cast<const double2*>(Le + 4 * F.eid(s));
       const double2 x = lp[0], y = lp[1];
       acc[0] += F.cw[s] * x.x; acc[1] += F.cw[s] * x.y; acc[2] += F.cw[s] * y.x; acc[3] += F.cw[s] * y.y;
     }
@@ -1423,7 +1432,7 @@ __device__ __forceinline__ void vertex_block2(int bk, double* lds, const T* __re
   // then every thread's share of the staged rows (at most RPT each) loaded
   // together before any is written to LDS: one memory round trip, not one per
   // row.
-  BlockFetch<TW, MV, ME> F;
+  BlockFetch<TW, MV, ME, PK> F;
   {
     const int ic = v0 + (sub < nb ? sub : nb), ic1 = v0 + (sub < nb ? sub + 1 : nb);   // past the block: empty
     F.i = sub;
@@ -1484,15 +1493,15 @@ __device__ __forceinline__ void vertex_block2(int bk, double* lds, const T* __re
   const double* Le = lds + 4 * na;
   for (int ib = 0; ib < nb; ib += VPR) {
     if (PF == 2) {
-      BlockFetch<TW, MV, ME> G;
+      BlockFetch<TW, MV, ME, PK> G;
       block_fetch<TW, LPV, MV, ME, PK>(G, ib + VPR + sub, v0, nb, lane, lp, lvcol, wfg, lecol, we, pk);
-      block_compute<T, TW, LPV, MV, ME>(F, v0, nb, o0, lane, Lv, Le, lvcol, wfg, lecol, we, cO, gm1, mode, R, wn, out,
-                                        a, b, dt_dev);
+      block_compute<T, TW, LPV, MV, ME, PK>(F, v0, nb, o0, lane, Lv, Le, lvcol, wfg, lecol, we, cO, gm1, mode, R, wn,
+                                            out, a, b, dt_dev);
       F = G;
     } else {
       if (ib > 0) block_fetch<TW, LPV, MV, ME, PK>(F, ib + sub, v0, nb, lane, lp, lvcol, wfg, lecol, we, pk);
-      block_compute<T, TW, LPV, MV, ME>(F, v0, nb, o0, lane, Lv, Le, lvcol, wfg, lecol, we, cO, gm1, mode, R, wn, out,
-                                        a, b, dt_dev);
+      block_compute<T, TW, LPV, MV, ME, PK>(F, v0, nb, o0, lane, Lv, Le, lvcol, wfg, lecol, we, cO, gm1, mode, R, wn,
+                                            out, a, b, dt_dev);
     }
   }
 }

@@ -92,7 +92,7 @@ struct fdu_solver {
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
   }
   int edge_variant = 1;    // 0: k_edge_flux, 1-2: k_edge_flux_lean (2: held to 4 waves per SIMD)
-  int vertex_variant = 17; // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair,
+  int vertex_variant = 16; // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair,
                            // 10-13: k_vertex_lds (12-13: blocks walked in reverse), 14-17: k_vertex_blk
                            // (16-17: packed first-round ids)
 };
