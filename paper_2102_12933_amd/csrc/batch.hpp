@@ -47,6 +47,65 @@ struct BatchInst {
 
 constexpr unsigned kWaitLimit = 1u << 22;
 
+// The instance table as the kernels read it: the same layout with every
+// pointer typed as a global-memory pointer.  Read through BatchInst the
+// pointers would be generic, and generic (flat) loads also count against the
+// LDS wait counter, so every LDS wait in the kernels would wait for all memory
+// loads in flight.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+struct BatchInstG {
+  gptr<const int> sten;
+  gptr<const double> geo;
+  gptr<const int> vptr;
+  gptr<const int> vcol;
+  gptr<const double> wfg;
+  gptr<const int> eptr;
+  gptr<const int> ecol;
+  gptr<const double> we;
+  gptr<const double> cO;
+  gptr<const double> hmin;
+  gptr<const int> gsrc;
+  gptr<const signed char> grefl;
+  gptr<const double> gstate;
+  gptr<const int> vblk;
+  gptr<const int> vb_own;
+  gptr<const int> vb_uvp;
+  gptr<const int> vb_uv;
+  gptr<const int> vb_uep;
+  gptr<const int> vb_ue;
+  gptr<const unsigned short> vb_lvcol;
+  gptr<const unsigned short> vb_lecol;
+  gptr<const PackedIds> vb_pk;
+  gptr<double> flux;
+  gptr<double> w;
+  gptr<double> w1;
+  gptr<double> w2;
+  int nv_real, nv_total, ne, ng;
+};
+static_assert(sizeof(BatchInstG) == sizeof(BatchInst) && offsetof(BatchInstG, w2) == offsetof(BatchInst, w2) &&
+                  offsetof(BatchInstG, ng) == offsetof(BatchInst, ng),
+              "the two views of an instance must share their layout");
+
+// Instance i of the table, its pointers derived from global-memory pointers.
+__device__ __forceinline__ BatchInst global_view(const BatchInst* __restrict__ inst, int i) {
+  const BatchInstG& G = reinterpret_cast<const BatchInstG*>(inst)[i];
+  BatchInst I;
+  I.sten = (const int*)G.sten; I.geo = (const double*)G.geo;
+  I.vptr = (const int*)G.vptr; I.vcol = (const int*)G.vcol; I.wfg = (const double*)G.wfg;
+  I.eptr = (const int*)G.eptr; I.ecol = (const int*)G.ecol; I.we = (const double*)G.we;
+  I.cO = (const double*)G.cO; I.hmin = (const double*)G.hmin;
+  I.gsrc = (const int*)G.gsrc; I.grefl = (const signed char*)G.grefl; I.gstate = (const double*)G.gstate;
+  I.vblk = (const int*)G.vblk; I.vb_own = (const int*)G.vb_own; I.vb_uvp = (const int*)G.vb_uvp;
+  I.vb_uv = (const int*)G.vb_uv; I.vb_uep = (const int*)G.vb_uep; I.vb_ue = (const int*)G.vb_ue;
+  I.vb_lvcol = (const unsigned short*)G.vb_lvcol; I.vb_lecol = (const unsigned short*)G.vb_lecol;
+  I.vb_pk = (const PackedIds*)G.vb_pk;
+  I.flux = (double*)G.flux; I.w = (double*)G.w; I.w1 = (double*)G.w1; I.w2 = (double*)G.w2;
+  I.nv_real = G.nv_real; I.nv_total = G.nv_total; I.ne = G.ne; I.ng = G.ng;
+  return I;
+}
+
 __device__ __forceinline__ void wait_count(unsigned* c, unsigned target, int* err) {
   if (threadIdx.x == 0) {
     unsigned it = 0;
@@ -117,7 +176,7 @@ __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict
     if (t >= total) return;
     const int j = find_slot(tb, 3 * n, t);
     const int p = j / n, i = j - p * n, local = t - tb[j];
-    const BatchInst& I = inst[i];
+    const BatchInst I = global_view(inst, i);
     double* wprev = k == 0 ? I.w : (k == 1 ? I.w1 : I.w2);
     double* wout = k == 0 ? I.w1 : (k == 1 ? I.w2 : I.w);
     if (PH <= 0 && p == 0) {
@@ -160,7 +219,7 @@ __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict
 
 // Vertex phase over all instances with the stencil halos staged in LDS: one
 // workgroup per vertex block; tile t of the phase maps to (instance, block).
-// The block kernel of vertex variant 17 (next round prefetched, packed ids).
+// The block kernel of vertex variant 16 (packed ids, 5 waves per SIMD).
 template <int LPV, int MV, int ME, int PF, int WPE, bool PK>
 __global__ void __launch_bounds__(256, WPE) k_batch_vertex_lds(const BatchInst* __restrict__ inst, int n,
                                                                const int* __restrict__ tb, Scheme S, int k, double a,
@@ -169,7 +228,7 @@ __global__ void __launch_bounds__(256, WPE) k_batch_vertex_lds(const BatchInst* 
   const int t = tb[2 * n] + blockIdx.x;
   if (t >= tb[3 * n]) return;
   const int j = find_slot(tb + 2 * n, n, t);
-  const BatchInst& I = inst[j];
+  const BatchInst I = global_view(inst, j);
   const double* wprev = k == 0 ? I.w : (k == 1 ? I.w1 : I.w2);
   double* wout = k == 0 ? I.w1 : (k == 1 ? I.w2 : I.w);
   vertex_block2<double, double, LPV, MV, ME, PF, PK>(t - tb[2 * n + j], lds, wprev, I.vblk, I.vb_own, I.vb_uvp,
@@ -188,7 +247,7 @@ __global__ void __launch_bounds__(256) k_batch_cfl(const BatchInst* __restrict__
   __shared__ double sm[256];
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     const int i = find_slot(tbc, n, t);
-    const BatchInst& I = inst[i];
+    const BatchInst I = global_view(inst, i);
     const int v = (t - tbc[i]) * 256 + threadIdx.x;
     double best = 1e300;
     if (v < I.nv_real) {

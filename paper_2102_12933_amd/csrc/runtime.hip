@@ -665,7 +665,7 @@ void batch_stage_vm(fdu_batch* b, int k, hipStream_t st) {
   if (t1 > 0) batch_stage_launch<EV, VM, 1>(b, k, st, (unsigned)t1);
   if (t2 > 0) {
     if (VM == 3)
-      hipLaunchKernelGGL((k_batch_vertex_lds<8, 3, 6, 2, 4, true>), dim3(t2), dim3(256),
+      hipLaunchKernelGGL((k_batch_vertex_lds<8, 3, 6, 1, 5, true>), dim3(t2), dim3(256),
                          (size_t)b->lds_rows * 4 * sizeof(double) + 2 * (kBlockVertices + 1) * sizeof(int), st,
                          b->dinst.p, n, b->tb.p, b->S, k, kRK[k][0],
                          kRK[k][1], b->dt.p);
