@@ -326,9 +326,11 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
 /* Kernel variants and autotuning.  Every variant computes the same residual
  * (the parity tests run each one); they differ in schedule and register use:
  *   edge:   0 = coefficient-form WENO, IEEE divisions; 1 = divided-difference
- *           WENO, one side's geometry live at a time, refined reciprocals;
- *           2 = variant 1 held to 4 waves per SIMD (no spills), the characteristic
- *           frame recomputed for the back projection instead of kept live;
+ *           WENO on the edge's six nodes, the two middle quadratics shared by
+ *           both sides (four per component instead of six), refined
+ *           reciprocals; 2 = divided-difference WENO one side at a time, held
+ *           to 4 waves per SIMD (no spills), the characteristic frame
+ *           recomputed for the back projection instead of kept live;
  *   vertex: 0 = 16 lanes per vertex, strided loops; 1, 2, 3 = 16, 32, 8 lanes
  *           per vertex, all index/weight loads issued before all gathers;
  *           4, 5 = strided loops with 8 and 4 lanes per vertex; 6, 7 = strided

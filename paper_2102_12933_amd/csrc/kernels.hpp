@@ -703,7 +703,91 @@ __device__ __forceinline__ double weno_dd_eval(const WenoDD& G, const double u[5
   return (n0 * ut[0] + n1 * ut[1] + n2 * ut[2]) * frcp(n0 + n1 + n2);
 }
 
-// Edge flux, register-lean variant: one side's WENO geometry live at a time,
+// Both sides at once on the edge's six nodes, in the left side's coordinates
+// s = (s0, s1, -1/2, 1/2, s4, s5).  The left side combines the quadratics on
+// nodes (0,1,2), (1,2,3), (2,3,4), the right side those on (5,4,3), (4,3,2),
+// (3,2,1): the middle two are the same polynomials for both sides, and their
+// value at the midpoint and smoothness indicator (the integral over the middle
+// interval of squared derivatives) do not change under the mirror, so four
+// quadratics are evaluated instead of six.  The twelve positive gaps and gap
+// products are inverted with one reciprocal as in weno_dd_geom.
+struct WenoDD2 {
+  double s0, s1, s4, s5;
+  double ig[5];   // 1/(s_{m+1} - s_m), ig[2] = 1
+  double ih[4];   // 1/(s_{m+2} - s_m)
+  double CL[3], CR[3];
+};
+
+__device__ __forceinline__ void weno_dd_geom2(double s0, double s1, double s4, double s5, WenoDD2& G) {
+  G.s0 = s0; G.s1 = s1; G.s4 = s4; G.s5 = s5;
+  const double a[12] = {s1 - s0,  -0.5 - s1, s4 - 0.5, s5 - s4,   -0.5 - s0, 0.5 - s1,
+                        s4 + 0.5, s5 - 0.5,  s4 - s0,  (0.5 - s0) * (s4 - s1), s5 - s1, (s5 + 0.5) * (s4 - s1)};
+  double p[12];
+  p[0] = a[0];
+#pragma unroll
+  for (int i = 1; i < 12; ++i) p[i] = p[i - 1] * a[i];
+  double inv = frcp(p[11]), ia[12];
+#pragma unroll
+  for (int i = 11; i > 0; --i) {
+    ia[i] = inv * p[i - 1];
+    inv *= a[i];
+  }
+  ia[0] = inv;
+  G.ig[0] = ia[0];
+  G.ig[1] = ia[1];
+  G.ig[2] = 1.0;
+  G.ig[3] = ia[2];
+  G.ig[4] = ia[3];
+  G.ih[0] = ia[4];
+  G.ih[1] = ia[5];
+  G.ih[2] = ia[6];
+  G.ih[3] = ia[7];
+  // left (nodes s0..s4): C0 = s3 s4 / ((s4 - s0)(s3 - s0)), C2 = s0 s1 / ((s4 - s0)(s4 - s1)), s3 = 1/2;
+  // right: the same with the mirrored nodes (-s5, -s4, -1/2, 1/2, -s1)
+  const double tl = ia[8] * ia[9], tr = ia[10] * ia[11];
+  G.CL[0] = 0.5 * s4 * (s4 - s1) * tl;
+  G.CL[2] = s0 * s1 * (0.5 - s0) * tl;
+  G.CL[1] = 1.0 - G.CL[0] - G.CL[2];
+  G.CR[0] = -0.5 * s1 * (s4 - s1) * tr;
+  G.CR[2] = s5 * s4 * (s5 + 0.5) * tr;
+  G.CR[1] = 1.0 - G.CR[0] - G.CR[2];
+}
+
+// Left and right midpoint values of one component from the six node values.
+template <int POW>
+__device__ __forceinline__ void weno_dd_eval2(const WenoDD2& G, const double u[6], double eps, double& ul,
+                                              double& ur) {
+  const double xs[6] = {G.s0, G.s1, -0.5, 0.5, G.s4, G.s5};
+  double dd[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) dd[m] = (u[m + 1] - u[m]) * G.ig[m];
+  double ut[4], b[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double a = xs[k], bb = xs[k + 1];
+    const double h2 = (dd[k + 1] - dd[k]) * G.ih[k];          // q''/2
+    const double d1 = dd[k] - h2 * (a + bb);                   // q'(0)
+    ut[k] = u[k] - dd[k] * a + h2 * a * bb;                    // q(0)
+    b[k] = fma(d1, d1, fma((13.0 / 3.0) * h2, h2, eps));
+    if (POW == 2) b[k] *= b[k];
+  }
+  {
+    const double n0 = G.CL[0] * b[1] * b[2];
+    const double n1 = G.CL[1] * b[0] * b[2];
+    const double n2 = G.CL[2] * b[0] * b[1];
+    ul = (n0 * ut[0] + n1 * ut[1] + n2 * ut[2]) * frcp(n0 + n1 + n2);
+  }
+  {
+    // the right side's sub-stencils 0, 1, 2 are quadratics 3, 2, 1
+    const double n0 = G.CR[0] * b[2] * b[1];
+    const double n1 = G.CR[1] * b[3] * b[1];
+    const double n2 = G.CR[2] * b[3] * b[2];
+    ur = (n0 * ut[3] + n1 * ut[2] + n2 * ut[1]) * frcp(n0 + n1 + n2);
+  }
+}
+
+// Edge flux, register-lean variant: with RF one side's WENO geometry live at a time,
+// otherwise both sides evaluated together (four quadratics per component);
 // divided-difference interpolants, refined reciprocals and square roots.
 // RF: recompute the characteristic frame for the back projection (from
 // reloaded end states) instead of keeping it in registers through the WENO.
@@ -737,22 +821,32 @@ __device__ __forceinline__ void edge_lean_body(const T* __restrict__ w, const in
   double x[4];
   weno_nodes(g, S, x);
   double cl[4], cr[4];
-  {
-    WenoDD G;
-    weno_dd_geom(x[0], x[1], x[2], G);
+  if constexpr (RF) {
+    {
+      WenoDD G;
+      weno_dd_geom(x[0], x[1], x[2], G);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const double u[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
-      cl[c] = weno_dd_eval<POW>(G, u, S.eps);
+      for (int c = 0; c < 4; ++c) {
+        const double u[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
+        cl[c] = weno_dd_eval<POW>(G, u, S.eps);
+      }
     }
-  }
-  {
-    WenoDD G;
-    weno_dd_geom(-x[3], -x[2], -x[1], G);
+    {
+      WenoDD G;
+      weno_dd_geom(-x[3], -x[2], -x[1], G);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double u[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
+        cr[c] = weno_dd_eval<POW>(G, u, S.eps);
+      }
+    }
+  } else {
+    WenoDD2 G;
+    weno_dd_geom2(x[0], x[1], x[2], x[3], G);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const double u[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
-      cr[c] = weno_dd_eval<POW>(G, u, S.eps);
+      const double u[6] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c], Cv[5][c]};
+      weno_dd_eval2<POW>(G, u, S.eps, cl[c], cr[c]);
     }
   }
   double wl[4], wr[4];

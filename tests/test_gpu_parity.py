@@ -364,9 +364,10 @@ def test_hilbert_order_variants(vertex):
 
 
 def test_edge_variant_two_matches_variant_one():
-    """Edge variant 2 recomputes the characteristic frame for the back
-    projection from the reloaded end states; the compiled arithmetic is not
-    the same instruction stream, so the fluxes agree with variant 1's to
+    """Edge variant 2 evaluates each side's WENO on its own and recomputes the
+    characteristic frame for the back projection from the reloaded end states;
+    variant 1 evaluates the two middle quadratics once for both sides.  The
+    arithmetic differs in order only, so the fluxes agree with variant 1's to
     rounding (walled and periodic meshes, both WENO powers)."""
     for c in (Case(33, True, 0, 5, "vortex", reorder=2), Case(20, False, 4, 5, "sod", reorder=2),
               Case(18, True, 0, 5, "vortex", weno_power=2)):

@@ -153,3 +153,30 @@ def test_sin_perturbed_stencils_order():
         u_err.append(np.abs(uniform_weno5(400)(u).numpy() - exact).mean())
     assert abs(_order(hs, nu_err) - 5.0) < 0.6, nu_err
     assert abs(_order(hs, u_err) - 1.0) < 0.4, u_err
+
+
+def test_middle_substencils_are_shared_by_the_two_sides():
+    """The left state of an edge interpolates on (L3, L2, L1, R1, R2), the right
+    state on the mirrored (R3, R2, R1, L1, L2).  The left's sub-stencils
+    (L2, L1, R1) and (L1, R1, R2) are the right's (R1, L1, L2) and (R2, R1, L1):
+    the same quadratics, evaluated at the same midpoint, with smoothness
+    indicators integrated over the same middle edge, so their values and
+    indicators agree between the sides (the edge kernel evaluates them once)."""
+    rng = np.random.default_rng(11)
+    n = 200
+    d = rng.uniform(0.5, 2.0, n)                       # middle-edge length
+    gaps = rng.uniform(0.3, 3.0, (n, 4)) * d[:, None]
+    s = np.stack([-d / 2 - gaps[:, 0] - gaps[:, 1], -d / 2 - gaps[:, 1], -d / 2,
+                  d / 2, d / 2 + gaps[:, 2], d / 2 + gaps[:, 2] + gaps[:, 3]], 1)
+    u = torch.from_numpy(rng.normal(size=(n, 6)))
+    left = NUWeno5(s[:, 0:5])
+    right = NUWeno5(-s[:, ::-1][:, 0:5])
+    ul, ur = u[:, 0:5], torch.flip(u, [1])[:, 0:5]
+    vl, _ = left._sub_values(ul)
+    vr, _ = right._sub_values(ur)
+    bl, br = left.smoothness(ul), right.smoothness(ur)
+    for kl, kr in ((1, 2), (2, 1)):
+        assert torch.allclose(vl[:, kl], vr[:, kr], rtol=1e-12, atol=1e-12)
+        assert torch.allclose(bl[:, kl], br[:, kr], rtol=1e-11, atol=1e-13)
+    # the outer ones are not shared
+    assert not torch.allclose(vl[:, 0], vr[:, 0], rtol=1e-3)
