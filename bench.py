@@ -379,14 +379,26 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # every edge-flux and vertex launch of the timed region is bracketed by HIP events on its stream
-    solver.kernel_timer_start(capacity=3 * args.steps + 8, phases=("edge", "vertex"))
+    # Every launch of the dominant kernel (the longer of the edge flux and the vertex step in the
+    # back-to-back times above; the roofline's kernel) in the timed region is bracketed by
+    # timing-only HIP events on its stream.  The other one is timed the same way in a separate,
+    # untimed run of the same steps: its events would add about 1% to the timed region.
+    dom = "vertex" if small["vertex"] >= small["edge"] else "edge"
+    other = "edge" if dom == "vertex" else "vertex"
+    solver.kernel_timer_start(capacity=3 * args.steps + 8, phases=(dom,))
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     kt, kcount = solver.kernel_timer_stop()
+    n_other = min(args.steps, 50)
+    solver.kernel_timer_start(capacity=3 * n_other + 8, phases=(other,))
+    for _ in range(n_other):
+        step()
+    torch.cuda.synchronize()
+    kt_o, kcount_o = solver.kernel_timer_stop()
+    kt[other], kcount[other] = kt_o[other], kcount_o[other]
     wr = w3[:A["nv_real"]]
     rho = wr[:, 0]
     p = 0.4 * (wr[:, 3] - 0.5 * (wr[:, 1] ** 2 + wr[:, 2] ** 2) / rho)
@@ -422,7 +434,6 @@ def main():
     for k in ("edge", "vertex"):
         ms = kt[k]
         kern[k] = dict(avg_ms=ms, launches=kcount[k], bytes=nb[k], gbs=nb[k] / (ms * 1e-3) / 1e9)
-    dom = max(("edge", "vertex"), key=lambda k: kt[k])
     names = dict(edge=EDGE_KERNELS[tune["edge"]], vertex=VERTEX_KERNELS[tune["vertex"]])
     traffic = traffic_from_profiles(names[dom], args.N, args.reorder)
     achieved = kern[dom]["gbs"]
@@ -445,7 +456,8 @@ def main():
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=names[dom], variant=tune[dom], avg_ms=round(kt[dom], 5), launches=kcount[dom],
                     algorithmic_bytes=nb[dom],
-                    timing="timing-only HIP events around every edge-flux and vertex launch in the timed region",
+                    timing=f"timing-only HIP events around every {dom} launch in the timed region",
+                    other_kernel_timing=f"{other}: the same events in a separate run of {n_other} of the same steps",
                     copy_gbs=copy_gbs)
     nv_real = A["nv_real"]
     value = nv_real * 3 * args.steps / el
