@@ -459,7 +459,7 @@ FDU_HD void edge_flux_one(const double W[6][4], const double g[6], const Scheme&
 // Vertex blocks of the LDS-staged vertex kernels: at most kBlockVertices
 // consecutive vertices and kBlockRows staged rows (32 bytes each) per block.
 constexpr int kBlockVertices = 256;
-constexpr int kBlockRows = 896;
+constexpr int kBlockRows = 928;
 
 // Packed stream ids of the block kernel (vertex variants 16-17).  For every
 // real vertex and each of its 8 lanes, one 12-byte record holds the
