@@ -312,6 +312,27 @@ def sod_state(mesh_or_xy, angle_deg: float = 30.0, center=(0.5, 0.5),
     return primitive_to_conservative(*prim, gamma=gamma)
 
 
+def square_sod_state(mesh_or_xy, half: float = 0.25, center=None,
+                     inside=(1.0, 0.0, 0.0, 1.0), outside=(0.125, 0.0, 0.0, 0.1),
+                     gamma: float = GAMMA) -> np.ndarray:
+    """Two-dimensional shock tube of Sec. 3.2: ``inside`` in the square
+    |x - cx| < half, |y - cy| < half, ``outside`` elsewhere.  The paper's domain
+    is the periodic box [-1, 1]^2 with the square at its centre; on a periodic
+    mesh of [0, 2]^2 the default centre is the box centre, which is the same
+    problem shifted by (1, 1)."""
+    if isinstance(mesh_or_xy, Mesh):
+        xy = mesh_or_xy.xy
+        if center is None:
+            center = (0.5 * mesh_or_xy.box[0], 0.5 * mesh_or_xy.box[1])
+    else:
+        xy = mesh_or_xy
+        if center is None:
+            raise ValueError("pass center with bare coordinates")
+    sq = (np.abs(xy[:, 0] - center[0]) < half) & (np.abs(xy[:, 1] - center[1]) < half)
+    prim = [np.where(sq, inside[k], outside[k]) for k in range(4)]
+    return primitive_to_conservative(*prim, gamma=gamma)
+
+
 def normal_shock_states(mach: float = 1.2, gamma: float = GAMMA):
     """Primitive (rho, u, v, p) on both sides of a stationary normal shock at x = 0
     with the flow in -x: upstream (x > 0) rho = 1, p = 1/gamma (sound speed 1),
