@@ -34,11 +34,14 @@ SOD_CFL = 0.2
 METRIC = "vertex-stage updates/sec + HBM GB/s vs peak; batched & adjoint vs plain path"
 
 
-def kernel_bytes(A, precision_bytes=8, blocks=None, packed=None):
-    """Algorithmic bytes per launch (each datum counted once).
+def kernel_bytes(A, precision_bytes=8, blocks=None, packed=None, wn_stages=3):
+    """Algorithmic bytes per launch as stored (each datum counted once), averaged
+    over the three stage launches of an SSP-RK3 step.
     edge:   per flux edge 6 int32 ids + 6 geometry values + 4 flux values written,
             plus every state row read once;
-    vertex: per real vertex two CSR pointers, c_O (2), w_n (4) and the output (4),
+    vertex: per real vertex two CSR pointers, c_O (2) and the output (4), w_n (4)
+            in the stages that read it (the first stage has a_0 = 0 and does
+            not: wn_stages = 2 of 3 for a whole step, 3 for the stage form alone),
             per vertex entry an int32 id + 2 weights, per edge entry an int32 id +
             1 weight, plus every state row and every flux row read once.
             LDS-staged variants (blocks given): 16-bit ids instead, plus per block
@@ -51,7 +54,8 @@ def kernel_bytes(A, precision_bytes=8, blocks=None, packed=None):
     nvt, nvr, nef, nzv, nze = A["nv_total"], A["nv_real"], A["ne_flux"], A["nnz_v"], A["nnz_e"]
     edge = nef * (6 * 4 + 6 * s + 4 * 8) + nvt * 4 * s
     ids = 4 if blocks is None else 2
-    vertex = nvr * (2 * 4 + 2 * 8 + 4 * s + 4 * s) + nzv * 2 * s + nze * s + nvt * 4 * s + nef * 4 * 8
+    vertex = (nvr * (2 * 4 + 2 * 8 + 4 * s) + nvr * 4 * s * wn_stages / 3.0 + nzv * 2 * s + nze * s + nvt * 4 * s
+              + nef * 4 * 8)
     if packed is None:
         vertex += (nzv + nze) * ids
     else:
@@ -61,8 +65,33 @@ def kernel_bytes(A, precision_bytes=8, blocks=None, packed=None):
     return dict(edge=edge, vertex=vertex)
 
 
+def survey_bytes_per_vertex_stage(A, precision_bytes=8, wn_stages=2):
+    """Algorithmic bytes per real vertex and stage of the vertex step in the
+    blueprint's unit count (int32 ids, each datum once, E = ne_flux / nv_real
+    edges per vertex): state 4s + CSR pointers 16 + ids (n_v + n_e) 4 +
+    weights (2 n_v + n_e) s + c_O 2s + flux rows 4 * 8 * E + w_n 4s (in
+    wn_stages of the 3 stages) + output 4s, with n_v, n_e the mean stencil
+    sizes of the mesh.  For 19 + 44 entries and E = 3 this is 1,132 B (w_n
+    counted in every stage)."""
+    s = precision_bytes
+    nvr = A["nv_real"]
+    nv_mean, ne_mean, E = A["nnz_v"] / nvr, A["nnz_e"] / nvr, A["ne_flux"] / nvr
+    return (4 * s + 16 + (nv_mean + ne_mean) * 4 + (2 * nv_mean + ne_mean) * s + 2 * s + 4 * 8 * E
+            + 4 * s * wn_stages / 3.0 + 4 * s)
+
+
+def survey_edge_bytes_per_vertex_stage(A, precision_bytes=8):
+    """The edge step's bytes per real vertex and stage in the blueprint's unit
+    count: state 4s + E (6 int32 ids + 6 arc coordinates + 2 direction values +
+    the 32-byte flux row written), E = ne_flux / nv_real."""
+    s = precision_bytes
+    E = A["ne_flux"] / A["nv_real"]
+    return 4 * s + E * (6 * 4 + 6 * s + 2 * s + 32)
+
+
 # vertex variants whose first-round ids are packed, and the entries a first round covers
-PACKED_VERTEX_VARIANTS = (16, 17)
+PACKED_VERTEX_VARIANTS = (4, 5)
+BLOCK_VERTEX_VARIANTS = (3, 4, 5)
 PACKED_ROUND = (24, 48)
 
 
@@ -77,19 +106,11 @@ def entries_past_first_round(A):
 
 
 # kernel (template instance) behind each variant number of the library
-EDGE_KERNELS = {0: "k_edge_flux<double, double>", 1: "k_edge_flux_lean<double, double, 1>",
-                2: "k_edge_flux_lean<double, double, 4>"}
-VERTEX_KERNELS = {0: "k_vertex<double, double, 16, false>", 1: "k_vertex_pipe<double, double, 16, 2, 3>",
-                  2: "k_vertex_pipe<double, double, 32, 1, 2>", 3: "k_vertex_pipe<double, double, 8, 3, 6>",
-                  4: "k_vertex<double, double, 8, false>", 5: "k_vertex<double, double, 4, false>",
-                  6: "k_vertex<double, double, 16, true>", 7: "k_vertex<double, double, 8, true>",
-                  8: "k_vertex_pair<double, double, 16, 3, 6>", 9: "k_vertex_pair<double, double, 8, 5, 11>",
-                  10: "k_vertex_lds<double, double, 8, 3, 6, 1, 5>", 11: "k_vertex_lds<double, double, 4, 5, 11, 1, 4>",
-                  12: "k_vertex_lds<double, double, 8, 3, 6, 1, 5>", 13: "k_vertex_lds<double, double, 4, 5, 11, 1, 4>",
-                  14: "k_vertex_blk<double, double, 8, 3, 6, 1, 5, false>",
-                  15: "k_vertex_blk<double, double, 8, 3, 6, 2, 4, false>",
-                  16: "k_vertex_blk<double, double, 8, 3, 6, 1, 5, true>",
-                  17: "k_vertex_blk<double, double, 8, 3, 6, 2, 4, true>"}
+EDGE_KERNELS = {0: "k_edge_flux<double, double>", 1: "k_edge_flux_lean<double, double>"}
+VERTEX_KERNELS = {0: "k_vertex<double, double, 16, false>", 1: "k_vertex<double, double, 8, false>",
+                  2: "k_vertex_pipe<double, double, 8, 3, 6>", 3: "k_vertex_lds<double, double, 8, 3, 6, 1, 5>",
+                  4: "k_vertex_blk<double, double, 8, 3, 6, 1, 5, true>",
+                  5: "k_vertex_blk<double, double, 8, 3, 6, 2, 4, true>"}
 KERNEL_SOURCES = ("csrc/kernels.hpp", "csrc/batch.hpp", "csrc/adjoint.hpp", "csrc/runtime.hip", "build.py")
 
 
@@ -145,6 +166,26 @@ def cpu_baseline(mesh, w_input, budget_s=15.0, patch=48):
                 sample=f"{len(sample)} real vertices ({patch}x{patch} block at the domain centre) of the same "
                        f"1025^2 workload, {n} residual+stage evaluations on the state after one GPU step, "
                        f"{el:.1f} s")
+
+
+def fallback_edges(prep, solver, states):
+    """Edges whose flux the positivity fallback changes, per stage input of one
+    step: the flux arrays of the solver and of a twin without the fallback
+    (same kernel variant, same arithmetic otherwise) are compared row by row;
+    a row differs only where an interpolated midpoint state was not physical."""
+    import torch
+    from paper_2102_12933_amd import fdu
+
+    twin = fdu.Solver(prep, device=0, positivity=0)
+    v = solver.variants()
+    twin.set_variants(v["edge"], v["vertex"])
+    counts = []
+    for w in states:
+        a = solver.edge_fluxes(w)
+        b = twin.edge_fluxes(w)
+        counts.append(int((~((a == b).all(1))).sum().item()))
+    del twin
+    return counts
 
 
 def bench_batched(n_inst, steps, cfl, edge_variant, vertex_variant, log):
@@ -408,6 +449,11 @@ def main():
     if not state_ok:
         raise RuntimeError("non-physical state after a step")
     log(f"timed {args.steps} steps: {el * 1e3:.2f} ms; live kernel means (ms) {kt}, launches {kcount}")
+    # does the positivity fallback (not in the paper) fire in the timed step?  (untimed check)
+    fallback = None
+    if solver.params["positivity"]:
+        fallback = fallback_edges(prep, solver, (w0, w1, w2))
+        log(f"positivity fallback: edges changed per stage input {fallback}")
 
     # the same steps captured in one HIP graph (launch gaps removed); reported beside the headline
     graph = None
@@ -427,16 +473,21 @@ def main():
         log(f"graph replay of {args.steps} steps: {elg * 1e3:.2f} ms")
         del g
 
-    blocks = solver.vertex_block_info() if tune["vertex"] >= 10 else None
+    blocks = solver.vertex_block_info() if tune["vertex"] in BLOCK_VERTEX_VARIANTS else None
     packed = entries_past_first_round(A) if tune["vertex"] in PACKED_VERTEX_VARIANTS else None
-    nb = kernel_bytes(A, blocks=blocks, packed=packed)
+    nb = kernel_bytes(A, blocks=blocks, packed=packed, wn_stages=2)
+    # the roofline's algorithmic bytes: the blueprint's per-vertex-stage figure
+    # (int32 ids, every datum once) times the real vertices one launch updates
+    per_unit = dict(vertex=survey_bytes_per_vertex_stage(A, 8, wn_stages=2),
+                    edge=survey_edge_bytes_per_vertex_stage(A, 8))
     kern = {}
     for k in ("edge", "vertex"):
         ms = kt[k]
         kern[k] = dict(avg_ms=ms, launches=kcount[k], bytes=nb[k], gbs=nb[k] / (ms * 1e-3) / 1e9)
     names = dict(edge=EDGE_KERNELS[tune["edge"]], vertex=VERTEX_KERNELS[tune["vertex"]])
     traffic = traffic_from_profiles(names[dom], args.N, args.reorder)
-    achieved = kern[dom]["gbs"]
+    alg_bytes = per_unit[dom] * A["nv_real"]
+    achieved = alg_bytes / (kt[dom] * 1e-3) / 1e9
     # context for the roof: what a plain 1 GiB device-to-device copy reaches on this GPU
     # (skipped in counter-calibration runs, whose only large copies must be the 512 MiB ones)
     copy_gbs = None
@@ -455,7 +506,10 @@ def main():
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=names[dom], variant=tune[dom], avg_ms=round(kt[dom], 5), launches=kcount[dom],
-                    algorithmic_bytes=nb[dom],
+                    algorithmic_bytes=round(alg_bytes), bytes_per_vertex_stage=round(per_unit[dom], 1),
+                    units_per_launch=int(A["nv_real"]),
+                    stored_bytes=round(nb[dom]), stored_gbs=round(kern[dom]["gbs"], 1),
+                    stored_frac=round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4),
                     timing=f"timing-only HIP events around every {dom} launch in the timed region",
                     other_kernel_timing=f"{other}: the same events in a separate run of {n_other} of the same steps",
                     copy_gbs=copy_gbs)
@@ -483,6 +537,7 @@ def main():
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in d.items()}
                     for k, d in kern.items()} | {"ghost_ms": round(small["ghost"], 5), "cfl_ms": round(small["cfl"], 5)},
         "vertex_blocks": blocks,
+        "positivity_fallback_edges": fallback,
         "graph_replay": graph,
         "autotune": {"edge_variant": tune["edge"], "vertex_variant": tune["vertex"],
                      "edge_ms": [round(t, 5) for t in tune["edge_ms"]],

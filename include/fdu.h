@@ -157,6 +157,10 @@ void fdu_prep_destroy(fdu_prep* prep);
 
 /* ------------------------------------------------------------------------
  * Solver: device-resident stencils and weights of one mesh instance.
+ * CSR pointers (vptr, eptr) are 32-bit offsets: a solver holds at most
+ * 2^31 - 1 vertex entries and as many edge entries (about 110 M real vertices
+ * with two-level stencils of 19 vertices and 44 edges); the prep refuses
+ * larger meshes with FDU_ERR_INVALID_ARG.
  * fdu_create selects hip_device and allocates nothing large.
  * fdu_upload_* copy host arrays (layouts as in fdu_prep_view, all in the
  * library's numbering) into library-owned device memory; they validate ids
@@ -194,31 +198,44 @@ fdu_status fdu_sizes(const fdu_solver* s, int64_t* nv_total, int64_t* nv_real, i
 /* ------------------------------------------------------------------------
  * Compute calls (asynchronous on stream, no allocation).
  *
- * fdu_fill_ghosts: rows [nv_real, nv_total) of w (device, in/out) := their
- *   mirror sources with the flagged momentum components negated.
- * fdu_edge_fluxes: r (device [ne_flux][4] double) := numerical flux
- *   projections along each flux edge from the state w (device, read; ghost
- *   rows must be filled).
- * fdu_residual: fills the ghost rows of w (device, in/out: only ghost rows are
- *   written), computes the edge fluxes into the solver's flux buffer and
- *   writes R (device [nv_real][4]) = dw/dt at the real vertices.
- * fdu_cfl_dt: dt_dev (device, one double) := cfl * min over real vertices of
- *   hmin_v / (|u_v| + c_v).
- * fdu_rk_stage: stage k in {0,1,2} of SSP-RK3 on the real rows:
+ * fdu_fill_ghosts (boundary conditions; Sec. 3.3 for the Dirichlet
+ *   inflow/outflow states, walls are not in the paper): rows [nv_real,
+ *   nv_total) of w (device, in/out) := their mirror sources with the flagged
+ *   momentum components negated, or the given Dirichlet states.
+ * fdu_edge_fluxes (Sec. 2.3.1 and the Appendix: the six-point curvilinear
+ *   stencil, NU-WENO5 of the characteristic variables at the edge midpoint,
+ *   then the numerical flux): r (device [ne_flux][4] double) := the flux
+ *   projections along each flux edge from the state w (device, read only;
+ *   its ghost rows must be filled).
+ * fdu_residual (Sec. 2.2.1, the least-squares divergence as the weight row of
+ *   the pseudo-inverse applied to the differenced vertex fluxes and the edge
+ *   projections; dw/dt = -div, Sec. 2.1): R (device [nv_real][4]) := dw/dt at
+ *   the real vertices for the state w (device [nv_total][4], read only: on
+ *   meshes with ghosts the library copies w's real rows into a state buffer it
+ *   allocated at fdu_finalize and fills that copy's ghost rows, so w's ghost
+ *   rows are neither read nor written).  The edge fluxes go to the solver's
+ *   flux buffer.
+ * fdu_cfl_dt (Sec. 3.1 names the CFL number; the formula is this library's
+ *   reading): dt_dev (device, one double) := cfl * min over real vertices of
+ *   hmin_v / (|u_v| + c_v), hmin_v the shortest edge at v.
+ * fdu_rk_stage (Sec. 3, the third-order TVD Runge-Kutta scheme, here the
+ *   Shu-Osher SSP-RK3): stage k in {0,1,2} on the real rows:
  *   w_out = a_k w_n + b_k (w_prev + dt R(w_prev)), (a,b) = (0,1), (3/4,1/4),
- *   (1/3,2/3); dt read from dt_dev (device).  w_prev's ghost rows are filled;
- *   w_out must not alias w_prev (other vertices gather from it) but may alias
- *   w_n (each vertex reads only its own row of w_n); w_n is unused at k = 0;
- *   w_out's ghost rows are not written.
- * fdu_rk_step: one full SSP-RK3 step in place on w (device [nv_total][4]),
- *   using scratch (device, two states [2][nv_total][4]); if cfl > 0 the step
- *   first sets *dt_dev from the CFL condition, otherwise it reads *dt_dev.
+ *   (1/3,2/3); dt read from dt_dev (device).  w_prev's ghost rows are filled
+ *   in place (the only rows of w_prev written); w_out must not alias w_prev
+ *   (other vertices gather from it) but may alias w_n (each vertex reads only
+ *   its own row of w_n); w_n is unused at k = 0; w_out's ghost rows are not
+ *   written.
+ * fdu_rk_step (Sec. 3): one full SSP-RK3 step in place on w (device
+ *   [nv_total][4]), using scratch (device, two states [2][nv_total][4]); if
+ *   cfl > 0 the step first sets *dt_dev from the CFL condition, otherwise it
+ *   reads *dt_dev.
  * Errors: FDU_ERR_STATE before fdu_finalize; FDU_ERR_INVALID_ARG for NULL
  * pointers or k out of range; FDU_ERR_HIP if a launch fails.
  */
 fdu_status fdu_fill_ghosts(fdu_solver* s, void* w, void* stream);
 fdu_status fdu_edge_fluxes(fdu_solver* s, const void* w, double* r, void* stream);
-fdu_status fdu_residual(fdu_solver* s, void* w, void* R, void* stream);
+fdu_status fdu_residual(fdu_solver* s, const void* w, void* R, void* stream);
 fdu_status fdu_cfl_dt(fdu_solver* s, const void* w, double cfl, double* dt_dev, void* stream);
 fdu_status fdu_rk_stage(fdu_solver* s, int k, const void* w_n, void* w_prev, void* w_out,
                         const double* dt_dev, void* stream);
@@ -233,25 +250,26 @@ fdu_status fdu_rk_step(fdu_solver* s, void* w, void* scratch, double cfl, double
  * fdu_residual_vjp: wbar (device [nv_total][4], state dtype) :=
  *   (dR/dw)^T Rbar for Rbar (device [nv_real][4]); ghost rows of wbar are zero
  *   (ghost states are copies of real ones and their cotangent is added to the
- *   source rows).  w's ghost rows are filled (as fdu_residual does); wbar must
- *   not alias w or Rbar.
+ *   source rows).  w is read only (its ghost rows are filled in the library's
+ *   copy, as in fdu_residual); wbar must not alias w or Rbar.
  * fdu_rk_stage_vjp: adjoint of fdu_rk_stage k with the scalar dt:
  *   wbar_prev := b_k obar + b_k dt (dR/dw_prev)^T obar (ghost rows zero) and,
  *   for k > 0, wbar_n += a_k obar on the real rows.  obar is [nv_total][4]
  *   (real rows used).
- * fdu_rk_step_vjp: adjoint of one fdu_rk_step at a fixed time step (dt on the
- *   device in dt_dev for the recomputed forward stages, and as the scalar dt):
- *   recomputes the stage states from w_n (in/out: ghost rows filled) and writes
+ * fdu_rk_step_vjp: adjoint of one fdu_rk_step at the fixed time step dt (one
+ *   value, written to a device scalar of the solver and used both for the
+ *   recomputed forward stages and for the reverse sweep): recomputes the stage
+ *   states from w_n (in/out: ghost rows filled) and writes
  *   wbar_n := (dw_{n+1}/dw_n)^T wbar_np1.  scratch: device, 4 states.
  * Errors: FDU_ERR_STATE if the adjoint is not enabled; FDU_ERR_INVALID_ARG for
  * NULL or aliased arguments.  Asynchronous on stream; no allocation.
  */
 fdu_status fdu_enable_adjoint(fdu_solver* s);
-fdu_status fdu_residual_vjp(fdu_solver* s, void* w, const void* Rbar, void* wbar, void* stream);
+fdu_status fdu_residual_vjp(fdu_solver* s, const void* w, const void* Rbar, void* wbar, void* stream);
 fdu_status fdu_rk_stage_vjp(fdu_solver* s, int k, void* w_prev, const void* obar, void* wbar_n, void* wbar_prev,
                             double dt, void* stream);
-fdu_status fdu_rk_step_vjp(fdu_solver* s, void* w_n, const void* wbar_np1, void* wbar_n, void* scratch,
-                           const double* dt_dev, double dt, void* stream);
+fdu_status fdu_rk_step_vjp(fdu_solver* s, void* w_n, const void* wbar_np1, void* wbar_n, void* scratch, double dt,
+                           void* stream);
 
 /* fdu_kernel_times: measurement aid.  Launches each kernel of a stage reps
  * times back to back on stream, bracketed by HIP events, and writes the mean
@@ -298,10 +316,10 @@ fdu_status fdu_kernel_timer_stop(fdu_solver* s, double* avg_ms, int* counts);
  *   vertex; 1: strided loops, 8 lanes; 2: pipelined loads, 8 lanes; vertex
  *   tile = passes x 256 / lanes; 3: one tile per vertex block of the
  *   instance with its stencil halo staged in LDS, the code of vertex variant
- *   16, schedules 1 and 2 only, FDU_ERR_UNSUPPORTED with 0).  Results equal
- *   the plain path's with vertex variant 0, 4, 3 and 10 (= 14-17)
- *   respectively, bit for bit (the edge phase runs edge
- *   variant 0's code when the instances use edge variant 0, else variant 1's).
+ *   4, schedules 1 and 2 only, FDU_ERR_UNSUPPORTED with 0).  Results equal
+ *   the plain path's with vertex variant 0, 1, 2 and 3 (= 4, 5) respectively,
+ *   bit for bit (the edge phase runs edge variant 0's code when the instances
+ *   use edge variant 0, else variant 1's).
  * fdu_batch_step: one SSP-RK3 step of every instance with its own dt =
  *   cfl * min hmin/(|u|+c) (computed on the device), asynchronous on stream.
  * fdu_batch_capture: records nsteps steps on stream (not the default stream)
@@ -328,36 +346,29 @@ fdu_status fdu_batch_info(const fdu_batch* b, int* schedule, int* total_tiles, i
  *   edge:   0 = coefficient-form WENO, IEEE divisions; 1 = divided-difference
  *           WENO on the edge's six nodes, the two middle quadratics shared by
  *           both sides (four per component instead of six), refined
- *           reciprocals; 2 = divided-difference WENO one side at a time, held
- *           to 4 waves per SIMD (no spills), the characteristic frame
- *           recomputed for the back projection instead of kept live;
- *   vertex: 0 = 16 lanes per vertex, strided loops; 1, 2, 3 = 16, 32, 8 lanes
- *           per vertex, all index/weight loads issued before all gathers;
- *           4, 5 = strided loops with 8 and 4 lanes per vertex; 6, 7 = strided
- *           loops with 16 and 8 lanes and non-temporal stencil-array loads;
- *           8, 9 = 16 and 8 lanes per vertex in pairs, each lane of a pair
- *           gathering one 16-byte half of a stencil row (half the gather
- *           instructions), all loads issued before the arithmetic;
- *           10, 11 = 8 and 4 lanes per vertex over vertex blocks whose
+ *           reciprocals and square roots;
+ *   vertex: 0, 1 = 16 and 8 lanes per vertex, strided loops over the CSR
+ *           rows; 2 = 8 lanes per vertex, all index/weight loads issued before
+ *           all gathers; 3 = 8 lanes per vertex over vertex blocks whose
  *           stencil halo (state and flux rows) is first staged in LDS, 16-bit
  *           block-local row indices (blocks are built at fdu_finalize; they
  *           are compact when the prep used the Hilbert order, reorder = 2);
- *           12, 13 = variants 10 and 11 with each XCD's range of blocks walked
- *           from its end (the rows the edge kernel wrote last come first);
- *           14, 15 = the blocks of variant 10 with their CSR pointers and own
- *           state rows also staged in LDS and the stage combine spread over 4
- *           lanes (15: the next round's index and weight loads issued before
- *           the current round is computed); 16, 17 = variants 14 and 15 with
- *           each lane's first-round row indices (3 state rows, 6 flux rows)
- *           packed 10 bits each into one 12-byte record per vertex and lane,
- *           built at fdu_finalize: one load instead of nine 16-bit gathers,
- *           kept packed until each position is used (variant 16 fits 5 waves
- *           per SIMD without spilling).
+ *           4, 5 = the blocks of variant 3 with their CSR pointers and own
+ *           state rows also staged in LDS, the stage combine spread over 4
+ *           lanes, and each lane's first-round row indices (3 state rows, 6
+ *           flux rows) packed 10 bits each into one 12-byte record per vertex
+ *           and lane, built at fdu_finalize: one load instead of nine 16-bit
+ *           gathers, kept packed until each position is used (4: one round at
+ *           a time, 5 waves per SIMD without spills; 5: the next round's loads
+ *           issued before the current round is computed, 4 waves per SIMD).
+ *           Variants 3, 4 and 5 sum the same terms in the same order (equal
+ *           results bit for bit).
  * fdu_set_variants / fdu_get_variants select and report them (n_edge, n_vertex:
- * how many exist); a new solver starts with edge 1 and vertex 16.  fdu_autotune times every edge variant and then every vertex
- * variant on the given state with fdu_kernel_times (reps launches each),
- * writes the mean times (ms) to times_ms[0 .. n_edge + n_vertex - 1] and keeps
- * the fastest of each; synchronous; w and scratch as for fdu_kernel_times. */
+ * how many exist); a new solver starts with edge 1 and vertex 4.  fdu_autotune
+ * times every edge variant and then every vertex variant on the given state
+ * with fdu_kernel_times (reps launches each), writes the mean times (ms) to
+ * times_ms[0 .. n_edge + n_vertex - 1] and keeps the fastest of each;
+ * synchronous; w and scratch as for fdu_kernel_times. */
 /* fdu_check_state: failure detection for long runs.  Counts the real rows of
  * w (device state, the solver's precision) that are not finite or not
  * physical (rho <= 0 or p <= 0), writes the count to *n_bad and the smallest

@@ -17,7 +17,7 @@ import torch
 class ResidualFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, w, solver):
-        w_in = w.detach().contiguous().clone()      # the library fills ghost rows in place
+        w_in = w.detach().contiguous()              # read only: the library fills ghost rows in a copy
         R = solver.residual(w_in)
         ctx.save_for_backward(w_in)
         ctx.solver = solver
@@ -26,7 +26,7 @@ class ResidualFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, Rbar):
         (w_in,) = ctx.saved_tensors
-        wbar = ctx.solver.residual_vjp(w_in.clone(), Rbar.contiguous())
+        wbar = ctx.solver.residual_vjp(w_in, Rbar.contiguous())
         return wbar, None
 
 
@@ -66,7 +66,7 @@ class RKUnroll(torch.autograd.Function):
                 solver.rk_step(w, scratch2, dt_dev)
                 states.append(w.clone())
             for j in reversed(range(stop - start)):
-                solver.rk_step_vjp(states[j], g, gn, scratch4, dt_dev, dt)
+                solver.rk_step_vjp(states[j], g, gn, scratch4, dt)
                 g, gn = gn, g
         return g, None, None, None, None
 

@@ -674,6 +674,11 @@ __global__ void __launch_bounds__(256) k_axpy_real(T* __restrict__ out, double a
 }
 
 // out[v] = a * x[v] on all rows
+// *p := x (one value; launched with one wave).
+__global__ void k_set_value(double* __restrict__ p, double x) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = x;
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) k_scale(T* __restrict__ out, double a, const T* __restrict__ x, int nv) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;

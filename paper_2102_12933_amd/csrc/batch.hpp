@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict
 
 // Vertex phase over all instances with the stencil halos staged in LDS: one
 // workgroup per vertex block; tile t of the phase maps to (instance, block).
-// The block kernel of vertex variant 16 (packed ids, 5 waves per SIMD).
+// The block kernel of vertex variant 4 (packed ids, 5 waves per SIMD).
 template <int LPV, int MV, int ME, int PF, int WPE, bool PK>
 __global__ void __launch_bounds__(256, WPE) k_batch_vertex_lds(const BatchInst* __restrict__ inst, int n,
                                                                const int* __restrict__ tb, Scheme S, int k, double a,

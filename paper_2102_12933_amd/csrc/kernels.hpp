@@ -461,7 +461,7 @@ FDU_HD void edge_flux_one(const double W[6][4], const double g[6], const Scheme&
 constexpr int kBlockVertices = 256;
 constexpr int kBlockRows = 928;
 
-// Packed stream ids of the block kernel (vertex variants 16-17).  For every
+// Packed stream ids of the block kernel (vertex variants 4-5).  For every
 // real vertex and each of its 8 lanes, one 12-byte record holds the
 // block-local ids of the lane's first-round entries: its 3 state-row slots,
 // then its 6 flux-row slots (entry pb + lane + 8 s of the vertex's range),
@@ -478,15 +478,6 @@ struct PackedIds {
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   const int q = nb >> 3, r = nb & 7, x = b & 7;
   return x * q + min(x, r) + (b >> 3);
-}
-
-// The same ranges per XCD, each walked from its end: a kernel launched after
-// one that used xcd_block starts on the rows the previous kernel touched last
-// (still in the XCD's L2 and the memory-side cache).
-__device__ __forceinline__ int xcd_block_rev(int b, int nb) {
-  const int q = nb >> 3, r = nb & 7, x = b & 7;
-  const int len = q + (x < r ? 1 : 0);
-  return x * q + min(x, r) + (len - 1 - (b >> 3));
 }
 
 // ----------------------------------------------------------------------------
@@ -638,70 +629,8 @@ __global__ void __launch_bounds__(256) k_vertex(const T* __restrict__ w, const i
 // For a sub-stencil with nodes (a, b, c) and values (ua, ub, uc):
 //   d1 = (ub - ua)/(b - a), d2 = (uc - ub)/(c - b), q'' = 2 (d2 - d1)/(c - a),
 //   q'(0) = d1 - (q''/2)(a + b),  q(0) = ua - d1 a + (q''/2) a b,
-// so a side needs the four inverse node gaps, three inverse double gaps, the
-// nodes and C_k (13 values) instead of 30 coefficients.
-struct WenoDD {
-  double x0, x1, x4;    // outer nodes (x2 = -1/2, x3 = 1/2)
-  double ig[4];         // 1/(x_{m+1} - x_m), m = 0..3 (ig[2] = 1)
-  double ih[3];         // 1/(x_{m+2} - x_m), m = 0..2
-  double C[3];
-};
-
-// The eight node gaps a side needs are positive and of moderate size (they are
-// normalised by the middle-edge length), so their inverses come from one
-// reciprocal of their product (prefix products, then one multiplication back
-// per gap: 1/a_i = (1/(a_1..a_i)) (a_1..a_{i-1})).
-__device__ __forceinline__ void weno_dd_geom(double x0, double x1, double x4, WenoDD& G) {
-  G.x0 = x0; G.x1 = x1; G.x4 = x4;
-  const double a[8] = {x1 - x0, -0.5 - x1, x4 - 0.5, -0.5 - x0, 0.5 - x1, x4 + 0.5, x4 - x0, (0.5 - x0) * (x4 - x1)};
-  double p[8];
-  p[0] = a[0];
-#pragma unroll
-  for (int i = 1; i < 8; ++i) p[i] = p[i - 1] * a[i];
-  double inv = frcp(p[7]), ia[8];
-#pragma unroll
-  for (int i = 7; i > 0; --i) {
-    ia[i] = inv * p[i - 1];
-    inv *= a[i];
-  }
-  ia[0] = inv;
-  G.ig[0] = ia[0];
-  G.ig[1] = ia[1];
-  G.ig[2] = 1.0;
-  G.ig[3] = ia[2];
-  G.ih[0] = ia[3];
-  G.ih[1] = ia[4];
-  G.ih[2] = ia[5];
-  // C0 = x3 x4 / ((x4 - x0)(x3 - x0)), C2 = x0 x1 / ((x4 - x0)(x4 - x1)), x3 = 1/2
-  const double t = ia[6] * ia[7];
-  G.C[0] = 0.5 * x4 * (x4 - x1) * t;
-  G.C[2] = x0 * x1 * (0.5 - x0) * t;
-  G.C[1] = 1.0 - G.C[0] - G.C[2];
-}
-
-// POW: the power of the smoothness indicators in the weights (1 or 2).
-template <int POW>
-__device__ __forceinline__ double weno_dd_eval(const WenoDD& G, const double u[5], double eps) {
-  const double xs[5] = {G.x0, G.x1, -0.5, 0.5, G.x4};
-  double dd[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) dd[m] = (u[m + 1] - u[m]) * G.ig[m];
-  double ut[3], b[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double a = xs[k], bb = xs[k + 1];
-    const double h2 = (dd[k + 1] - dd[k]) * G.ih[k];          // q''/2
-    const double d1 = dd[k] - h2 * (a + bb);                   // q'(0)
-    ut[k] = u[k] - dd[k] * a + h2 * a * bb;                    // q(0)
-    // q'(0)^2 + (13/12) q''^2 with q'' = 2 h2
-    b[k] = fma(d1, d1, fma((13.0 / 3.0) * h2, h2, eps));
-    if (POW == 2) b[k] *= b[k];
-  }
-  const double n0 = G.C[0] * b[1] * b[2];
-  const double n1 = G.C[1] * b[0] * b[2];
-  const double n2 = G.C[2] * b[0] * b[1];
-  return (n0 * ut[0] + n1 * ut[1] + n2 * ut[2]) * frcp(n0 + n1 + n2);
-}
+// so the interpolants need the inverse node gaps, inverse double gaps, the
+// nodes and C_k instead of the 30 coefficients of a side.
 
 // Both sides at once on the edge's six nodes, in the left side's coordinates
 // s = (s0, s1, -1/2, 1/2, s4, s5).  The left side combines the quadratics on
@@ -709,8 +638,10 @@ __device__ __forceinline__ double weno_dd_eval(const WenoDD& G, const double u[5
 // (3,2,1): the middle two are the same polynomials for both sides, and their
 // value at the midpoint and smoothness indicator (the integral over the middle
 // interval of squared derivatives) do not change under the mirror, so four
-// quadratics are evaluated instead of six.  The twelve positive gaps and gap
-// products are inverted with one reciprocal as in weno_dd_geom.
+// quadratics are evaluated instead of six.  The twelve gaps and gap products
+// are positive and of moderate size (normalised by the middle-edge length), so
+// their inverses come from one reciprocal of their product (prefix products,
+// then one multiplication back per gap: 1/a_i = (1/(a_1..a_i)) (a_1..a_{i-1})).
 struct WenoDD2 {
   double s0, s1, s4, s5;
   double ig[5];   // 1/(s_{m+1} - s_m), ig[2] = 1
@@ -786,12 +717,10 @@ __device__ __forceinline__ void weno_dd_eval2(const WenoDD2& G, const double u[6
   }
 }
 
-// Edge flux, register-lean variant: with RF one side's WENO geometry live at a time,
-// otherwise both sides evaluated together (four quadratics per component);
-// divided-difference interpolants, refined reciprocals and square roots.
-// RF: recompute the characteristic frame for the back projection (from
-// reloaded end states) instead of keeping it in registers through the WENO.
-template <class T, class TG, int POW, bool RF>
+// Edge flux, register-lean variant: both sides' WENO evaluated together (four
+// quadratics per component), divided-difference interpolants, refined
+// reciprocals and square roots.
+template <class T, class TG, int POW>
 __device__ __forceinline__ void edge_lean_body(const T* __restrict__ w, const int* __restrict__ sten,
                                                const TG* __restrict__ geo, double* __restrict__ r, int e,
                                                const Scheme& S) {
@@ -821,26 +750,7 @@ __device__ __forceinline__ void edge_lean_body(const T* __restrict__ w, const in
   double x[4];
   weno_nodes(g, S, x);
   double cl[4], cr[4];
-  if constexpr (RF) {
-    {
-      WenoDD G;
-      weno_dd_geom(x[0], x[1], x[2], G);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const double u[5] = {Cv[0][c], Cv[1][c], Cv[2][c], Cv[3][c], Cv[4][c]};
-        cl[c] = weno_dd_eval<POW>(G, u, S.eps);
-      }
-    }
-    {
-      WenoDD G;
-      weno_dd_geom(-x[3], -x[2], -x[1], G);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const double u[5] = {Cv[5][c], Cv[4][c], Cv[3][c], Cv[2][c], Cv[1][c]};
-        cr[c] = weno_dd_eval<POW>(G, u, S.eps);
-      }
-    }
-  } else {
+  {
     WenoDD2 G;
     weno_dd_geom2(x[0], x[1], x[2], x[3], G);
 #pragma unroll
@@ -856,13 +766,6 @@ __device__ __forceinline__ void edge_lean_body(const T* __restrict__ w, const in
       wl[k] = cl[k];
       wr[k] = cr[k];
     }
-  } else if (RF) {
-    double a[4], b[4];
-    load4(w, opaque(id[2]), a);
-    load4(w, opaque(id[3]), b);
-    const Frame F2 = roe_frame<double, true>(a, b, nx, ny, S.gm1);
-    from_char(F2, cl, wl);
-    from_char(F2, cr, wr);
   } else {
     from_char(F, cl, wl);
     from_char(F, cr, wr);
@@ -881,23 +784,22 @@ __device__ __forceinline__ void edge_lean_body(const T* __restrict__ w, const in
 
 // The WENO power is uniform over a launch: one branch instead of a select per
 // smoothness indicator.
-template <class T, class TG, bool RF = false>
+template <class T, class TG>
 __device__ __forceinline__ void edge_lean_item(const T* __restrict__ w, const int* __restrict__ sten,
                                                const TG* __restrict__ geo, double* __restrict__ r, int e,
                                                const Scheme& S) {
   if (S.power == 2)
-    edge_lean_body<T, TG, 2, RF>(w, sten, geo, r, e, S);
+    edge_lean_body<T, TG, 2>(w, sten, geo, r, e, S);
   else
-    edge_lean_body<T, TG, 1, RF>(w, sten, geo, r, e, S);
+    edge_lean_body<T, TG, 1>(w, sten, geo, r, e, S);
 }
 
-// WPE: waves per SIMD the register allocation is held to (1: unconstrained).
-template <class T, class TG, int WPE>
-__global__ void __launch_bounds__(256, WPE) k_edge_flux_lean(const T* __restrict__ w, const int* __restrict__ sten,
+template <class T, class TG>
+__global__ void __launch_bounds__(256) k_edge_flux_lean(const T* __restrict__ w, const int* __restrict__ sten,
                                                              const TG* __restrict__ geo, double* __restrict__ r,
                                                              int ne, Scheme S) {
   const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (e < ne) edge_lean_item<T, TG, (WPE >= 4)>(w, sten, geo, r, e, S);
+  if (e < ne) edge_lean_item<T, TG>(w, sten, geo, r, e, S);
 }
 
 // Vertex step, software-pipelined: every lane first loads the ids and weights
@@ -1014,153 +916,6 @@ __global__ void __launch_bounds__(256) k_vertex_pipe(const T* __restrict__ w, co
                                                      double a, double b, const double* __restrict__ dt_dev) {
   const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   vertex_pipe_item<T, TW, LPV, MV, ME>(w, vptr, vcol, wfg, eptr, ecol, we, cO, r, nreal, gm1, mode, R, wn, out, a, b,
-                                       dt_dev, t / LPV, t % LPV);
-}
-
-// Vertex step on half rows.  The texture data path returns about one cache
-// line per cycle for a gather, so a wave-wide 16-byte gather whose 64 lanes
-// hit 64 different rows costs ~64 cycles, and a 32-byte row needs two of
-// them.  Here two adjacent lanes share each stencil entry and load one 16-byte
-// half of its row each: one gather instruction covers 32 rows in 32 lines.
-// Lane parity h owns components 2h and 2h+1 of the accumulated divergence;
-// for the vertex terms the two lanes swap halves (a DPP lane permutation, no
-// memory) so that each can evaluate the Euler fluxes of the full state.
-__device__ __forceinline__ double pair_swap(double x) {
-  // quad_perm(1, 0, 3, 2): lane i reads lane i ^ 1
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ void load_half(const double* __restrict__ w, int v, int h, double q[2]) {
-  const double2 a = reinterpret_cast<const double2*>(w + 4 * (size_t)v)[h];
-  q[0] = a.x; q[1] = a.y;
-}
-__device__ __forceinline__ void load_half(const float* __restrict__ w, int v, int h, double q[2]) {
-  const float2 a = reinterpret_cast<const float2*>(w + 4 * (size_t)v)[h];
-  q[0] = a.x; q[1] = a.y;
-}
-__device__ __forceinline__ void store_half(double* __restrict__ w, int v, int h, double a, double b) {
-  reinterpret_cast<double2*>(w + 4 * (size_t)v)[h] = make_double2(a, b);
-}
-__device__ __forceinline__ void store_half(float* __restrict__ w, int v, int h, double a, double b) {
-  reinterpret_cast<float2*>(w + 4 * (size_t)v)[h] = make_float2((float)a, (float)b);
-}
-
-// Accumulates wf (f_j - f_O) + wg (g_j - g_O) for components (2h, 2h+1) from
-// this lane's half row x of w_j (the partner lane holds the other half).
-__device__ __forceinline__ void pair_vertex_term(const double x[2], int h, double gm1, double wf, double wg,
-                                                 const double f0[2], const double g0[2], bool use, double acc[2]) {
-  const double y0 = pair_swap(x[0]), y1 = pair_swap(x[1]);
-  const double q0 = h ? y0 : x[0], q1 = h ? y1 : x[1], q2 = h ? x[0] : y0, q3 = h ? x[1] : y1;
-  const double ir = 1.0 / q0;
-  const double u = q1 * ir, v = q2 * ir;
-  const double p = gm1 * (q3 - 0.5 * (q1 * u + q2 * v));
-  const double ep = q3 + p;
-  // h = 0: f = (m_x, m_x u + p), g = (m_y, m_y u); h = 1: f = (m_x v, (E+p) u), g = (m_y v + p, (E+p) v)
-  const double fa = h ? q1 * v : q1, fb = h ? ep * u : q1 * u + p;
-  const double ga = h ? q2 * v + p : q2, gb = h ? ep * v : q2 * u;
-  if (use) {
-    acc[0] += wf * (fa - f0[0]) + wg * (ga - g0[0]);
-    acc[1] += wf * (fb - f0[1]) + wg * (gb - g0[1]);
-  }
-}
-
-template <class T, class TW, int LPV, int MV, int ME>
-__device__ __forceinline__ void vertex_pair_item(const T* __restrict__ w, const int* __restrict__ vptr,
-                                                 const int* __restrict__ vcol, const TW* __restrict__ wfg,
-                                                 const int* __restrict__ eptr, const int* __restrict__ ecol,
-                                                 const TW* __restrict__ we, const double* __restrict__ cO,
-                                                 const double* __restrict__ r, int nreal, double gm1, int mode,
-                                                 T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
-                                                 double a, double b, const double* __restrict__ dt_dev, int v,
-                                                 int lane) {
-  constexpr int NS = LPV / 2;   // entry slots per pass
-  const int h = lane & 1, slot = lane >> 1;
-  const bool active = v < nreal;
-  const int vv = active ? v : 0;
-  int vb = 0, ve = 0, eb = 0, ee = 0;
-  if (active) {
-    vb = vptr[v]; ve = vptr[v + 1];
-    eb = eptr[v]; ee = eptr[v + 1];
-  }
-  int jv[MV], ke[ME];
-  double wf[MV], wg[MV], cw[ME];
-#pragma unroll
-  for (int s = 0; s < MV; ++s) {
-    const int p = vb + slot + s * NS;
-    jv[s] = p < ve ? vcol[p] : -1;
-    wf[s] = p < ve ? (double)wfg[2 * (size_t)p] : 0.0;
-    wg[s] = p < ve ? (double)wfg[2 * (size_t)p + 1] : 0.0;
-  }
-#pragma unroll
-  for (int s = 0; s < ME; ++s) {
-    const int p = eb + slot + s * NS;
-    ke[s] = p < ee ? ecol[p] : -1;
-    cw[s] = p < ee ? (double)we[p] : 0.0;
-  }
-  double hv[MV][2], hr[ME][2];
-#pragma unroll
-  for (int s = 0; s < MV; ++s) load_half(w, jv[s] >= 0 ? jv[s] : vv, h, hv[s]);
-#pragma unroll
-  for (int s = 0; s < ME; ++s) load_half(r, ke[s] >= 0 ? ke[s] : 0, h, hr[s]);
-  double q0[4], f0[4], g0[4];
-  load4(w, vv, q0);
-  euler_fg(q0, gm1, f0, g0);
-  const double f0h[2] = {h ? f0[2] : f0[0], h ? f0[3] : f0[1]};
-  const double g0h[2] = {h ? g0[2] : g0[0], h ? g0[3] : g0[1]};
-  double acc[2] = {0.0, 0.0};
-#pragma unroll
-  for (int s = 0; s < MV; ++s) pair_vertex_term(hv[s], h, gm1, wf[s], wg[s], f0h, g0h, jv[s] >= 0, acc);
-#pragma unroll
-  for (int s = 0; s < ME; ++s) {
-    acc[0] += cw[s] * hr[s][0];
-    acc[1] += cw[s] * hr[s][1];
-  }
-  // tails (rare: stencils larger than the unrolled slots); both lanes of a
-  // pair run the same trip count, so the half swap always finds its partner
-  for (int p = vb + slot + MV * NS; p < ve; p += NS) {
-    double x[2];
-    load_half(w, vcol[p], h, x);
-    pair_vertex_term(x, h, gm1, (double)wfg[2 * (size_t)p], (double)wfg[2 * (size_t)p + 1], f0h, g0h, true, acc);
-  }
-  for (int p = eb + slot + ME * NS; p < ee; p += NS) {
-    double x[2];
-    load_half(r, ecol[p], h, x);
-    const double c = (double)we[p];
-    acc[0] += c * x[0];
-    acc[1] += c * x[1];
-  }
-  // reduce over the lanes of equal parity
-#pragma unroll
-  for (int m = LPV / 2; m >= 2; m >>= 1) {
-    acc[0] += __shfl_xor(acc[0], m, LPV);
-    acc[1] += __shfl_xor(acc[1], m, LPV);
-  }
-  if (!active || slot != 0) return;
-  const double cx = cO[2 * (size_t)v], cy = cO[2 * (size_t)v + 1];
-  const double ra = -(acc[0] - (cx * f0h[0] + cy * g0h[0]));
-  const double rb = -(acc[1] - (cx * f0h[1] + cy * g0h[1]));
-  if (mode == 0) {
-    store_half(R, v, h, ra, rb);
-  } else {
-    const double dt = *dt_dev;
-    double n[2] = {0.0, 0.0};
-    if (a != 0.0) load_half(wn, v, h, n);
-    const double qa = h ? q0[2] : q0[0], qb = h ? q0[3] : q0[1];
-    store_half(out, v, h, a * n[0] + b * (qa + dt * ra), a * n[1] + b * (qb + dt * rb));
-  }
-}
-
-template <class T, class TW, int LPV, int MV, int ME>
-__global__ void __launch_bounds__(256) k_vertex_pair(const T* __restrict__ w, const int* __restrict__ vptr,
-                                                     const int* __restrict__ vcol, const TW* __restrict__ wfg,
-                                                     const int* __restrict__ eptr, const int* __restrict__ ecol,
-                                                     const TW* __restrict__ we, const double* __restrict__ cO,
-                                                     const double* __restrict__ r, int nreal, double gm1, int mode,
-                                                     T* __restrict__ R, const T* __restrict__ wn, T* __restrict__ out,
-                                                     double a, double b, const double* __restrict__ dt_dev) {
-  const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  vertex_pair_item<T, TW, LPV, MV, ME>(w, vptr, vcol, wfg, eptr, ecol, we, cO, r, nreal, gm1, mode, R, wn, out, a, b,
                                        dt_dev, t / LPV, t % LPV);
 }
 
@@ -1348,9 +1103,9 @@ __global__ void __launch_bounds__(256, WPE) k_vertex_lds(const T* __restrict__ w
                                                          const double* __restrict__ r, double gm1, int mode,
                                                          T* __restrict__ R, const T* __restrict__ wn,
                                                          T* __restrict__ out, double a, double b,
-                                                         const double* __restrict__ dt_dev, int rev) {
+                                                         const double* __restrict__ dt_dev) {
   extern __shared__ double lds[];   // [rows][4]: the block's state rows, then its flux rows
-  const int bk = rev ? xcd_block_rev(blockIdx.x, gridDim.x) : xcd_block(blockIdx.x, gridDim.x);
+  const int bk = xcd_block(blockIdx.x, gridDim.x);
   vertex_lds_block<T, TW, LPV, MV, ME, PF>(bk, lds, w, blk, uvp, uv, uep, ue, vptr,
                                            lvcol, wfg, eptr, lecol, we, cO, r, gm1, mode, R, wn, out, a, b, dt_dev);
 }

@@ -3,6 +3,7 @@
 // stencils with Catmull-Rom arc-length coordinates (Sec. 2.3.1), vertex and
 // edge ordering.  Runs once per mesh; the weights depend on geometry only.
 #include <algorithm>
+#include <climits>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -707,11 +708,16 @@ extern "C" fdu_status fdu_prep_build(fdu_prep** out, int64_t nv_total, int64_t n
     // CSR in the new numbering, entries sorted by column
     P->vptr.assign(nv_real + 1, 0);
     P->eptr.assign(nv_real + 1, 0);
+    // accumulated in 64 bits: the library's CSR pointers are 32-bit offsets
+    int64_t nvsum = 0, nesum = 0;
     for (int64_t i = 0; i < nv_real; ++i) {
       const VertexRow& r = rows[perm[i]];
-      P->vptr[i + 1] = P->vptr[i] + (int32_t)r.V.size();
-      P->eptr[i + 1] = P->eptr[i] + (int32_t)r.E.size();
-      if ((int64_t)P->vptr[i + 1] < 0 || (int64_t)P->eptr[i + 1] < 0) throw Error(FDU_ERR_INVALID_ARG, "stencils too large");
+      nvsum += (int64_t)r.V.size();
+      nesum += (int64_t)r.E.size();
+      if (nvsum > INT32_MAX || nesum > INT32_MAX)
+        throw Error(FDU_ERR_INVALID_ARG, "stencils too large: more than 2^31 - 1 entries");
+      P->vptr[i + 1] = (int32_t)nvsum;
+      P->eptr[i + 1] = (int32_t)nesum;
     }
     P->nnz_v = P->vptr[nv_real];
     P->nnz_e = P->eptr[nv_real];

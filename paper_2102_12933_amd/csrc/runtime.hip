@@ -73,13 +73,18 @@ struct fdu_solver {
   DevBuf<double> gstate;     // [ng][4] Dirichlet ghost states (rows of other ghosts unused)
   int64_t n_dirichlet = 0;
   DevBuf<double> geo, wfg, we, cO, hmin, flux, part;
+  // meshes with ghosts: a state-sized copy that fdu_residual and
+  // fdu_residual_vjp fill (real rows copied, ghost rows filled) so that the
+  // caller's state stays read-only
+  DevBuf<unsigned char> wcopy;
+  DevBuf<double> dt_adj;     // fdu_rk_step_vjp: the step's dt on the device (adjoint set-up)
   DevBuf<unsigned long long> chk;   // fdu_check_state: count, first bad row
   DevBuf<float> geo32, wfg32, we32;
   int cfl_blocks = 0;
   // vertex blocks with their stencil halos (LDS-staged vertex variants)
   DevBuf<int32_t> vblk, vb_own, vb_uvp, vb_uv, vb_uep, vb_ue;
   DevBuf<uint16_t> vb_lvcol, vb_lecol;
-  DevBuf<PackedIds> vb_pk;   // packed first-round ids per real vertex and lane (vertex variants 16-17)
+  DevBuf<PackedIds> vb_pk;   // packed first-round ids per real vertex and lane (vertex variants 4-5)
   int n_vblocks = 0, vb_rows_max = 0;
   // live kernel timer (fdu_kernel_timer_start/stop): event pairs recorded
   // around each launch of the ghost, edge, vertex and CFL kernels
@@ -91,10 +96,9 @@ struct fdu_solver {
     for (auto& v : timer_ev)
       for (hipEvent_t e : v) (void)hipEventDestroy(e);
   }
-  int edge_variant = 1;    // 0: k_edge_flux, 1-2: k_edge_flux_lean (2: held to 4 waves per SIMD)
-  int vertex_variant = 16; // 0, 4-7: k_vertex (loops), 1-3: k_vertex_pipe, 8-9: k_vertex_pair,
-                           // 10-13: k_vertex_lds (12-13: blocks walked in reverse), 14-17: k_vertex_blk
-                           // (16-17: packed first-round ids)
+  int edge_variant = 1;    // 0: k_edge_flux, 1: k_edge_flux_lean
+  int vertex_variant = 4;  // 0-1: k_vertex (strided loops, 16 and 8 lanes), 2: k_vertex_pipe,
+                           // 3: k_vertex_lds, 4-5: k_vertex_blk (packed first-round ids; 5: prefetch)
 };
 
 namespace {
@@ -183,17 +187,15 @@ void fill_ghosts_t(fdu_solver* s, T* w, hipStream_t st) {
   launch_check();
 }
 
-constexpr int kEdgeVariants = 3;
-constexpr int kVertexVariants = 18;
+constexpr int kEdgeVariants = 2;
+constexpr int kVertexVariants = 6;
 
 template <class T, class TG>
 void edge_flux_launch(fdu_solver* s, const T* w, const TG* geo, double* r, hipStream_t st) {
   const Scheme S = scheme_of(s);
   const dim3 grid(nblocks(s->ne_flux)), block(256);
   if (s->edge_variant == 1)
-    hipLaunchKernelGGL((k_edge_flux_lean<T, TG, 1>), grid, block, 0, st, w, s->sten.p, geo, r, (int)s->ne_flux, S);
-  else if (s->edge_variant == 2)
-    hipLaunchKernelGGL((k_edge_flux_lean<T, TG, 4>), grid, block, 0, st, w, s->sten.p, geo, r, (int)s->ne_flux, S);
+    hipLaunchKernelGGL((k_edge_flux_lean<T, TG>), grid, block, 0, st, w, s->sten.p, geo, r, (int)s->ne_flux, S);
   else
     hipLaunchKernelGGL((k_edge_flux<T, TG>), grid, block, 0, st, w, s->sten.p, geo, r, (int)s->ne_flux, S);
 }
@@ -219,32 +221,23 @@ void vertex_pipe_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, 
                      wn, out, a, b, dt);
 }
 
-template <class T, class TW, int LPV, int MV, int ME>
-void vertex_pair_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
-                        double a, double b, const double* dt, hipStream_t st) {
-  const unsigned nb = nblocks(s->nv_real * LPV);
-  hipLaunchKernelGGL((k_vertex_pair<T, TW, LPV, MV, ME>), dim3(nb), dim3(256), 0, st, w, s->vptr.p, s->vcol.p, wfg,
-                     s->eptr.p, s->ecol.p, we, s->cO.p, s->flux.p, (int)s->nv_real, s->params.gamma - 1.0, mode, R,
-                     wn, out, a, b, dt);
-}
-
 template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE>
 void vertex_lds_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
-                       double a, double b, const double* dt, hipStream_t st, int rev = 0) {
+                       double a, double b, const double* dt, hipStream_t st) {
   if (s->n_vblocks == 0) return;
   const size_t lds = (size_t)s->vb_rows_max * 4 * sizeof(double);
   hipLaunchKernelGGL((k_vertex_lds<T, TW, LPV, MV, ME, PF, WPE>), dim3(s->n_vblocks), dim3(256), lds, st, w, s->vblk.p,
                      s->vb_uvp.p, s->vb_uv.p, s->vb_uep.p, s->vb_ue.p, s->vptr.p, s->vb_lvcol.p, wfg, s->eptr.p,
-                     s->vb_lecol.p, we, s->cO.p, s->flux.p, s->params.gamma - 1.0, mode, R, wn, out, a, b, dt, rev);
+                     s->vb_lecol.p, we, s->cO.p, s->flux.p, s->params.gamma - 1.0, mode, R, wn, out, a, b, dt);
 }
 
 template <class T, class TW, int LPV, int MV, int ME, int PF, int WPE, bool PK>
 void vertex_blk_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
                        double a, double b, const double* dt, hipStream_t st) {
   if (s->n_vblocks == 0) return;
-  // the kernel stages at most 3 rows per thread and one pointer pair per thread (+1)
+  // the kernel stages at most ceil(kBlockRows / 256) = 4 rows per thread and one pointer pair per thread (+1)
   if (s->vb_rows_max > kBlockRows || kBlockVertices > 256)
-    throw Error(FDU_ERR_UNSUPPORTED, "vertex blocks exceed the staging capacity of vertex variants 14-17");
+    throw Error(FDU_ERR_UNSUPPORTED, "vertex blocks exceed the staging capacity of vertex variants 4-5");
   if (PK && s->vb_pk.n != (size_t)s->nv_real * kPackLPV)
     throw Error(FDU_ERR_STATE, "packed vertex-block ids were not built");
   const size_t lds = (size_t)s->vb_rows_max * 4 * sizeof(double) + 2 * (kBlockVertices + 1) * sizeof(int);
@@ -267,23 +260,11 @@ template <class T, class TW>
 void vertex_launch(fdu_solver* s, const T* w, const TW* wfg, const TW* we, int mode, T* R, const T* wn, T* out,
                    double a, double b, const double* dt, hipStream_t st) {
   switch (s->vertex_variant) {
-    case 1: vertex_pipe_launch<T, TW, 16, 2, 3>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 2: vertex_pipe_launch<T, TW, 32, 1, 2>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 3: vertex_pipe_launch<T, TW, 8, 3, 6>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 4: vertex_loop_launch<T, TW, 8, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 5: vertex_loop_launch<T, TW, 4, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 6: vertex_loop_launch<T, TW, 16, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 7: vertex_loop_launch<T, TW, 8, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 8: vertex_pair_launch<T, TW, 16, 3, 6>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 9: vertex_pair_launch<T, TW, 8, 5, 11>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 10: vertex_lds_launch<T, TW, 8, 3, 6, 1, 5>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 11: vertex_lds_launch<T, TW, 4, 5, 11, 1, 4>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 12: vertex_lds_launch<T, TW, 8, 3, 6, 1, 5>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st, 1); break;
-    case 13: vertex_lds_launch<T, TW, 4, 5, 11, 1, 4>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st, 1); break;
-    case 14: vertex_blk_launch<T, TW, 8, 3, 6, 1, 5, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 15: vertex_blk_launch<T, TW, 8, 3, 6, 2, 4, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 16: vertex_blk_launch<T, TW, 8, 3, 6, 1, 5, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
-    case 17: vertex_blk_launch<T, TW, 8, 3, 6, 2, 4, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 1: vertex_loop_launch<T, TW, 8, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 2: vertex_pipe_launch<T, TW, 8, 3, 6>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 3: vertex_lds_launch<T, TW, 8, 3, 6, 1, 5>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 4: vertex_blk_launch<T, TW, 8, 3, 6, 1, 5, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
+    case 5: vertex_blk_launch<T, TW, 8, 3, 6, 2, 4, true>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st); break;
     default: vertex_loop_launch<T, TW, 16, false>(s, w, wfg, we, mode, R, wn, out, a, b, dt, st);
   }
 }
@@ -311,11 +292,22 @@ void cfl_t(fdu_solver* s, const T* w, double cfl, double* dt, hipStream_t st) {
   launch_check();
 }
 
+// The state the residual reads: w itself when the mesh has no ghosts, else the
+// solver's copy of w's real rows with the ghost rows filled (w is not written).
 template <class T>
-void residual_t(fdu_solver* s, T* w, T* R, hipStream_t st) {
-  fill_ghosts_t<T>(s, w, st);
-  edge_flux_t<T>(s, w, s->flux.p, st);
-  vertex_t<T>(s, w, 0, R, nullptr, nullptr, 0.0, 0.0, nullptr, st);
+const T* ghosted_state(fdu_solver* s, const T* w, hipStream_t st) {
+  if (s->ng == 0) return w;
+  T* c = reinterpret_cast<T*>(s->wcopy.p);
+  FDU_HIP(hipMemcpyAsync(c, w, 4 * sizeof(T) * (size_t)s->nv_real, hipMemcpyDeviceToDevice, st));
+  fill_ghosts_t<T>(s, c, st);
+  return c;
+}
+
+template <class T>
+void residual_t(fdu_solver* s, const T* w, T* R, hipStream_t st) {
+  const T* wg = ghosted_state<T>(s, w, st);
+  edge_flux_t<T>(s, wg, s->flux.p, st);
+  vertex_t<T>(s, wg, 0, R, nullptr, nullptr, 0.0, 0.0, nullptr, st);
 }
 
 const double kRK[3][2] = {{0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
@@ -507,6 +499,7 @@ void build_adjoint(fdu_solver* s) {
   s->rbar.alloc(4 * ne);
   s->slots.alloc(24 * ne);
   s->vtmp.alloc(4 * nv);
+  s->dt_adj.alloc(1);
   s->adjoint = true;
 }
 
@@ -516,13 +509,12 @@ void ready_adjoint(const fdu_solver* s) {
 }
 
 // out = alpha (dR/dw)^T Rbar + beta add (real rows of add; add may be null);
-// ghost rows of out are zero.  w's ghost rows are filled first.
+// ghost rows of out are zero.  w's ghost rows must be filled.
 template <class T>
-void residual_vjp_t(fdu_solver* s, T* w, const T* Rbar, T* out, double alpha, const T* add, double beta,
+void residual_vjp_t(fdu_solver* s, const T* w, const T* Rbar, T* out, double alpha, const T* add, double beta,
                     hipStream_t st) {
   const Scheme S = scheme_of(s);
   const int ne = (int)s->ne_flux, nv = (int)s->nv_total, nr = (int)s->nv_real;
-  fill_ghosts_t<T>(s, w, st);
   constexpr int kLanes = 8;   // lanes per edge / vertex in the transposed gathers
   if (s->prec == FDU_F64) {
     hipLaunchKernelGGL((k_edge_cot<T, double, kLanes>), dim3(nblocks((int64_t)ne * kLanes)), dim3(256), 0, st,
@@ -553,6 +545,7 @@ template <class T>
 void rk_stage_vjp_t(fdu_solver* s, int k, T* wprev, const T* obar, T* wbar_n, T* wbar_prev, double dt,
                     hipStream_t st) {
   const double a = kRK[k][0], b = kRK[k][1];
+  fill_ghosts_t<T>(s, wprev, st);
   residual_vjp_t<T>(s, wprev, obar, wbar_prev, b * dt, obar, b, st);
   if (a != 0.0) {
     hipLaunchKernelGGL(k_axpy_real<T>, dim3(nblocks(s->nv_real)), dim3(256), 0, st, wbar_n, a, obar,
@@ -562,18 +555,22 @@ void rk_stage_vjp_t(fdu_solver* s, int k, T* wprev, const T* obar, T* wbar_n, T*
 }
 
 // Adjoint of one SSP-RK3 step at a fixed dt: recompute the stage states from
-// w_n, then run the stages backwards.  scratch holds 4 states.
+// w_n with the same dt (written to the device once, so the recomputed forward
+// stages and the reverse sweep cannot use different values), then run the
+// stages backwards.  scratch holds 4 states.
 template <class T>
-void rk_step_vjp_t(fdu_solver* s, T* wn, const T* wbar_np1, T* wbar_n, T* scratch, const double* dt_dev, double dt,
-                   hipStream_t st) {
+void rk_step_vjp_t(fdu_solver* s, T* wn, const T* wbar_np1, T* wbar_n, T* scratch, double dt, hipStream_t st) {
   const size_t S4 = 4 * (size_t)s->nv_total;
   T* w1 = scratch;
   T* w2 = scratch + S4;
   T* g2 = scratch + 2 * S4;
   T* g1 = scratch + 3 * S4;
-  rk_stage_t<T>(s, 0, wn, wn, w1, dt_dev, st);
-  rk_stage_t<T>(s, 1, wn, w1, w2, dt_dev, st);
-  // wbar_n := 1/3 wbar_np1 (real rows), ghost rows 0
+  hipLaunchKernelGGL(k_set_value, dim3(1), dim3(64), 0, st, s->dt_adj.p, dt);
+  launch_check();
+  rk_stage_t<T>(s, 0, wn, wn, w1, s->dt_adj.p, st);
+  rk_stage_t<T>(s, 1, wn, w1, w2, s->dt_adj.p, st);
+  // wbar_n := 0 on every row; the 1/3 wbar_np1 term of the last stage is
+  // added by that stage's adjoint (its a_2 axpy)
   hipLaunchKernelGGL(k_scale<T>, dim3(nblocks(s->nv_total)), dim3(256), 0, st, wbar_n, 0.0, wbar_np1,
                      (int)s->nv_total);
   launch_check();
@@ -925,6 +922,7 @@ fdu_status fdu_finalize(fdu_solver* s) {
     s->cfl_blocks = (int)std::min<int64_t>(1024, (s->nv_real + 255) / 256);
     s->part.alloc(s->cfl_blocks);
     s->chk.alloc(2);
+    if (s->ng > 0) s->wcopy.alloc(4 * (size_t)s->nv_total * (s->prec == FDU_F64 ? sizeof(double) : sizeof(float)));
     build_vertex_blocks(s);
     s->finalized = true;
   });
@@ -997,15 +995,15 @@ fdu_status fdu_edge_fluxes(fdu_solver* s, const void* w, double* r, void* stream
   });
 }
 
-fdu_status fdu_residual(fdu_solver* s, void* w, void* R, void* stream) {
+fdu_status fdu_residual(fdu_solver* s, const void* w, void* R, void* stream) {
   return guard([&] {
     ready(s);
     need(w && R, "NULL argument");
     DeviceGuard dg(s->device);
     if (s->prec == FDU_F64)
-      residual_t<double>(s, (double*)w, (double*)R, (hipStream_t)stream);
+      residual_t<double>(s, (const double*)w, (double*)R, (hipStream_t)stream);
     else
-      residual_t<float>(s, (float*)w, (float*)R, (hipStream_t)stream);
+      residual_t<float>(s, (const float*)w, (float*)R, (hipStream_t)stream);
   });
 }
 
@@ -1057,17 +1055,19 @@ fdu_status fdu_enable_adjoint(fdu_solver* s) {
   });
 }
 
-fdu_status fdu_residual_vjp(fdu_solver* s, void* w, const void* Rbar, void* wbar, void* stream) {
+fdu_status fdu_residual_vjp(fdu_solver* s, const void* w, const void* Rbar, void* wbar, void* stream) {
   return guard([&] {
     ready_adjoint(s);
     need(w && Rbar && wbar, "NULL argument");
     need(wbar != w && wbar != Rbar, "wbar must not alias w or Rbar");
     DeviceGuard dg(s->device);
+    hipStream_t st = (hipStream_t)stream;
     if (s->prec == FDU_F64)
-      residual_vjp_t<double>(s, (double*)w, (const double*)Rbar, (double*)wbar, 1.0, nullptr, 0.0,
-                             (hipStream_t)stream);
+      residual_vjp_t<double>(s, ghosted_state<double>(s, (const double*)w, st), (const double*)Rbar, (double*)wbar,
+                             1.0, nullptr, 0.0, st);
     else
-      residual_vjp_t<float>(s, (float*)w, (const float*)Rbar, (float*)wbar, 1.0, nullptr, 0.0, (hipStream_t)stream);
+      residual_vjp_t<float>(s, ghosted_state<float>(s, (const float*)w, st), (const float*)Rbar, (float*)wbar, 1.0,
+                            nullptr, 0.0, st);
   });
 }
 
@@ -1089,19 +1089,19 @@ fdu_status fdu_rk_stage_vjp(fdu_solver* s, int k, void* w_prev, const void* obar
   });
 }
 
-fdu_status fdu_rk_step_vjp(fdu_solver* s, void* w_n, const void* wbar_np1, void* wbar_n, void* scratch,
-                           const double* dt_dev, double dt, void* stream) {
+fdu_status fdu_rk_step_vjp(fdu_solver* s, void* w_n, const void* wbar_np1, void* wbar_n, void* scratch, double dt,
+                           void* stream) {
   return guard([&] {
     ready_adjoint(s);
-    need(w_n && wbar_np1 && wbar_n && scratch && dt_dev, "NULL argument");
+    need(w_n && wbar_np1 && wbar_n && scratch, "NULL argument");
     need(wbar_n != wbar_np1, "wbar_n must not alias wbar_np1");
     need(std::isfinite(dt), "dt must be finite");
     DeviceGuard dg(s->device);
     if (s->prec == FDU_F64)
-      rk_step_vjp_t<double>(s, (double*)w_n, (const double*)wbar_np1, (double*)wbar_n, (double*)scratch, dt_dev, dt,
+      rk_step_vjp_t<double>(s, (double*)w_n, (const double*)wbar_np1, (double*)wbar_n, (double*)scratch, dt,
                             (hipStream_t)stream);
     else
-      rk_step_vjp_t<float>(s, (float*)w_n, (const float*)wbar_np1, (float*)wbar_n, (float*)scratch, dt_dev, dt,
+      rk_step_vjp_t<float>(s, (float*)w_n, (const float*)wbar_np1, (float*)wbar_n, (float*)scratch, dt,
                            (hipStream_t)stream);
   });
 }

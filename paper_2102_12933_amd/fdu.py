@@ -84,7 +84,7 @@ _SIGS = {
     "fdu_batch_info": (I32, [VP, P(I32), P(I32), P(I32), P(I32), P(I32), P(I32)]),
     "fdu_residual_vjp": (I32, [VP, VP, VP, VP, VP]),
     "fdu_rk_stage_vjp": (I32, [VP, I32, VP, VP, VP, VP, D, VP]),
-    "fdu_rk_step_vjp": (I32, [VP, VP, VP, VP, VP, VP, D, VP]),
+    "fdu_rk_step_vjp": (I32, [VP, VP, VP, VP, VP, D, VP]),
 }
 
 _lib = None
@@ -195,6 +195,7 @@ class Solver:
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         self.prec = F64 if precision == "f64" else F32
         p = default_params(**params)
+        self.params = {name: getattr(p, name) for name, _ in Params._fields_}
         h = C.c_void_p()
         _call("fdu_create", C.byref(h), device, self.prec, C.byref(p))
         self.handle = h
@@ -300,12 +301,12 @@ class Solver:
         _call("fdu_rk_stage_vjp", self.handle, int(k), self._state(w_prev), self._state(obar), wn,
               self._state(wbar_prev), float(dt), _stream())
 
-    def rk_step_vjp(self, w_n, wbar_np1, wbar_n, scratch, dt_dev, dt: float):
+    def rk_step_vjp(self, w_n, wbar_np1, wbar_n, scratch, dt: float):
         if not (scratch.is_cuda and scratch.dtype == self.dtype and scratch.is_contiguous()
                 and scratch.numel() >= 16 * self.nv_total):
             raise ValueError("scratch must hold four states")
         _call("fdu_rk_step_vjp", self.handle, self._state(w_n), self._state(wbar_np1), self._state(wbar_n),
-              C.c_void_p(scratch.data_ptr()), self._dt(dt_dev), float(dt), _stream())
+              C.c_void_p(scratch.data_ptr()), float(dt), _stream())
 
     # -- kernel variants
     def set_variants(self, edge: int, vertex: int):

@@ -43,6 +43,20 @@ def test_kernel_bytes_counts_every_datum_once():
     assert n4["edge"] == 330 * (24 + 24 + 32) + 120 * 16
 
 
+def test_blueprint_unit_count():
+    """The roofline's per-vertex-stage bytes: 1,132 B for the vertex step with a
+    19-vertex, 44-edge stencil and 3 flux edges per vertex (w_n in every stage),
+    w_n's 32 B in two of three stages for a whole step, and 392 B for the edge step."""
+    n = 1000
+    A = dict(nv_total=n, nv_real=n, ne_flux=3 * n, nnz_v=19 * n, nnz_e=44 * n)
+    assert bench.survey_bytes_per_vertex_stage(A, 8, wn_stages=3) == pytest.approx(1132.0)
+    assert bench.survey_bytes_per_vertex_stage(A, 8, wn_stages=2) == pytest.approx(1132.0 - 32.0 / 3)
+    assert bench.survey_edge_bytes_per_vertex_stage(A, 8) == pytest.approx(392.0)
+    # stage-averaged w_n in the stored count as well
+    A2 = dict(A, nv_total=n)
+    assert bench.kernel_bytes(A2, wn_stages=2)["vertex"] == pytest.approx(bench.kernel_bytes(A2)["vertex"] - n * 32 / 3)
+
+
 def test_entries_past_first_round():
     import numpy as np
     # three real vertices with 30, 10, 24 vertex entries and 50, 48, 60 edge entries, one ghost
@@ -51,8 +65,9 @@ def test_entries_past_first_round():
 
 
 def test_every_variant_names_a_kernel():
-    assert set(bench.EDGE_KERNELS) == {0, 1, 2}
-    assert set(bench.VERTEX_KERNELS) == set(range(18))
+    assert set(bench.EDGE_KERNELS) == {0, 1}
+    assert set(bench.VERTEX_KERNELS) == set(range(6))
+    assert set(bench.PACKED_VERTEX_VARIANTS) <= set(bench.BLOCK_VERTEX_VARIANTS) <= set(bench.VERTEX_KERNELS)
     assert all(k.startswith("k_") for k in list(bench.EDGE_KERNELS.values()) + list(bench.VERTEX_KERNELS.values()))
 
 

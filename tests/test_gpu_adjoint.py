@@ -90,8 +90,7 @@ def test_rk_step_vjp_matches_oracle(N, per, G, deg, state):
     wn = c.dev(c.w0)
     out = torch.empty_like(wn)
     scratch = torch.empty(4 * c.m.nv, 4, dtype=torch.float64, device="cuda")
-    dt_dev = torch.full((1,), dt, dtype=torch.float64, device="cuda")
-    c.s.rk_step_vjp(wn, c.dev(ybar), out, scratch, dt_dev, dt)
+    c.s.rk_step_vjp(wn, c.dev(ybar), out, scratch, dt)
     err = rel_err_per_component(out.cpu().numpy(), ref.numpy()[c.perm])
     print("rk step vjp rel err", err)
     assert err.max() <= TOL

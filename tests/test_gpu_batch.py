@@ -55,7 +55,7 @@ def test_batch_equals_plain(edge_variant, schedule, ept, vp, vmode):
     fdu = _fdu()
     # the plain path's vertex kernel with the same lanes and load order sums in the same order
     # the batch's lean edge phase is edge variant 1's code
-    inst = build_instances(SPECS, edge_variant, vertex_variant={0: 0, 1: 4, 2: 3, 3: 10}[vmode])
+    inst = build_instances(SPECS, edge_variant, vertex_variant=vmode)
     ref = plain_steps(inst, 3, 0.5)
     b = fdu.Batch([s for s, _ in inst])
     b.set_schedule(schedule, ept, vp, vmode)
@@ -136,7 +136,7 @@ def test_full_batch_workload_sampled():
         w0 = torch.from_numpy(np.ascontiguousarray(vortex_state(m, beta=sp["beta"], mach=sp["mach"])[perm])).cuda()
         inst.append((s, w0))
     sample = [0, 17, 40, 63]
-    for schedule, vmode, plain_vertex in ((1, 3, 10), (0, 2, 3)):
+    for schedule, vmode, plain_vertex in ((1, 3, 3), (0, 2, 2)):
         for s, _ in inst:
             s.set_variants(1, plain_vertex)
         ref = plain_steps([inst[i] for i in sample], 3, 0.2)

@@ -174,15 +174,15 @@ def test_rk_stage_matches_oracle_stage(sod24_p5):
 
 @pytest.mark.parametrize("params", [dict(weno_power=2), dict(riemann=1), dict(positivity=0), dict(interpolation=1),
                                     dict(uniform_weno=1), dict(interpolation=1, uniform_weno=1)])
-@pytest.mark.parametrize("edge", [0, 1, 2])
+@pytest.mark.parametrize("edge", [0, 1])
 def test_parameter_switches(params, edge):
     c = Case(20, True, 0, 5, "vortex", **params)
-    c.s.set_variants(edge, 10)
+    c.s.set_variants(edge, 3)
     err = _residual_err(c)
     print(params, edge, err)
     assert err.max() <= TOL
     c2 = Case(16, False, 4, 5, "sod", **params)
-    c2.s.set_variants(edge, 3)
+    c2.s.set_variants(edge, 2)
     err2 = _residual_err(c2)
     assert err2.max() <= TOL
 
@@ -248,7 +248,7 @@ def sod1025_prep():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("edge,vertex", [(1, 10), (2, 12), (1, 14), (2, 15), (1, 16), (2, 17), (1, 3)])
+@pytest.mark.parametrize("edge,vertex", [(1, 4), (1, 5), (1, 3), (0, 2)])
 def test_full_size_sod_sampled(sod1025_prep, edge, vertex):
     """1025^2 rotated Sod (1.05M real vertices) in the bench's launch shape
     (Hilbert order, the kernel variants its autotuner chooses between): one
@@ -295,7 +295,7 @@ def test_full_size_sod_sampled(sod1025_prep, edge, vertex):
     assert err1.max() <= 1e-14
 
 
-@pytest.mark.parametrize("edge,vertex", [(e, v) for e in range(3) for v in range(18)])
+@pytest.mark.parametrize("edge,vertex", [(e, v) for e in range(2) for v in range(6)])
 def test_kernel_variants(vortex33_p5, sod24_p5, edge, vertex):
     """Every kernel variant computes the same residual (to the parity bar)."""
     for c in (vortex33_p5, sod24_p5):
@@ -353,7 +353,7 @@ def test_live_kernel_timer(sod24_p5):
     assert avg["ghost"] == 0.0 and avg["cfl"] == 0.0 and avg["vertex"] > 0.0
 
 
-@pytest.mark.parametrize("vertex", [0, 3, 10, 11, 12, 13, 14, 15, 16, 17])
+@pytest.mark.parametrize("vertex", range(6))
 def test_hilbert_order_variants(vertex):
     """Hilbert vertex order (compact vertex blocks for the LDS-staged variants):
     residual and one RK stage against the oracle, walled and periodic meshes."""
@@ -363,32 +363,14 @@ def test_hilbert_order_variants(vertex):
         assert err.max() <= TOL, err.max()
 
 
-def test_edge_variant_two_matches_variant_one():
-    """Edge variant 2 evaluates each side's WENO on its own and recomputes the
-    characteristic frame for the back projection from the reloaded end states;
-    variant 1 evaluates the two middle quadratics once for both sides.  The
-    arithmetic differs in order only, so the fluxes agree with variant 1's to
-    rounding (walled and periodic meshes, both WENO powers)."""
-    for c in (Case(33, True, 0, 5, "vortex", reorder=2), Case(20, False, 4, 5, "sod", reorder=2),
-              Case(18, True, 0, 5, "vortex", weno_power=2)):
-        w = c.w_dev()
-        c.s.fill_ghosts(w)
-        out = {}
-        for ev in (1, 2):
-            c.s.set_variants(ev, 15)
-            out[ev] = c.s.edge_fluxes(w).cpu().numpy()
-        err = rel_err_per_component(out[2], out[1])
-        assert err.max() <= 1e-14, err
-
-
 def test_block_variants_match_the_lds_variant():
-    """Variants 14 and 15 (pointers and own rows also staged in LDS, the stage
-    combine spread over 4 lanes) and 16 and 17 (the same with packed first-round
-    ids) evaluate the same terms in the same order as variant 10: residual and
-    all three stage types agree bit for bit."""
+    """Variants 4 and 5 (pointers and own rows also staged in LDS, the stage
+    combine spread over 4 lanes, packed first-round ids) evaluate the same terms
+    in the same order as variant 3: residual and all three stage types agree
+    bit for bit."""
     for c in (Case(33, True, 0, 5, "vortex", reorder=2), Case(20, False, 4, 5, "sod", reorder=2)):
         outs = {}
-        for v in (10, 14, 15, 16, 17):
+        for v in (3, 4, 5):
             c.s.set_variants(1, v)
             w = c.w_dev()
             R = c.s.residual(w)
@@ -399,10 +381,10 @@ def test_block_variants_match_the_lds_variant():
                 c.s.rk_stage(k, w, w, out, dt)
                 st.append(out[:c.m.nv_real].clone())
             outs[v] = (R, st)
-        for v in (14, 15, 16, 17):
-            assert torch.equal(outs[v][0], outs[10][0]), v
+        for v in (4, 5):
+            assert torch.equal(outs[v][0], outs[3][0]), v
             for k in range(3):
-                assert torch.equal(outs[v][1][k], outs[10][1][k]), (v, k)
+                assert torch.equal(outs[v][1][k], outs[3][1][k]), (v, k)
 
 
 def test_block_variants_on_one_level_stencils():
@@ -413,7 +395,7 @@ def test_block_variants_on_one_level_stencils():
     info = c.s.vertex_block_info()
     assert info["n_blocks"] < c.m.nv_real // 100, info
     ref = None
-    for v in (10, 14, 15, 16, 17):
+    for v in (3, 4, 5):
         c.s.set_variants(1, v)
         err = _residual_err(c)
         assert err.max() <= TOL, (v, err)
@@ -423,7 +405,7 @@ def test_block_variants_on_one_level_stencils():
         assert torch.equal(R, ref), v
 
 
-@pytest.mark.parametrize("vertex", [0, 3, 10, 14, 16])
+@pytest.mark.parametrize("vertex", [0, 2, 3, 4])
 def test_artificial_edges_residual_and_stage(vertex):
     """Degree-3 one-level stencils completed with artificial edges (Sec. 2.2.2):
     residual and one RK stage against the oracle built the same way."""
@@ -444,13 +426,13 @@ def test_two_level_degrees_four_and_six(deg):
     if deg == 4:        # degree 6 is not determined next to a mirrored wall (tested on the CPU)
         cases.append(Case(16, False, 4, deg, "sod", reorder=2))
     for c in cases:
-        for v in (3, 10):
+        for v in (2, 3):
             c.s.set_variants(1, v)
             err = _residual_err(c)
             assert err.max() <= TOL, (deg, v, err.max())
 
 
-@pytest.mark.parametrize("edge,vertex", [(0, 0), (1, 3), (1, 10)])
+@pytest.mark.parametrize("edge,vertex", [(0, 0), (1, 2), (1, 4)])
 def test_free_stream_preserved_on_the_gpu(edge, vertex):
     """A uniform state is a steady solution: the residual vanishes to rounding
     (Sec. 2.2.1: the differenced right-hand side is zero and every edge flux is
@@ -499,3 +481,67 @@ def test_checkpoint_resume_is_bitwise(tmp_path):
     for _ in range(5):
         c.s.rk_step(b2, scr, dt, cfl=0.5)
     assert torch.equal(a, b2)
+
+
+def test_positivity_fallback_on_the_gpu():
+    """A density dip on the two middle vertices of a straight, equally spaced
+    edge stencil makes every NU-WENO5 sub-stencil negative at the midpoint
+    (the oracle pin of the fallback): with the fallback the GPU edge flux of that
+    edge equals the oracle's (the exact normal flux of the common end state),
+    and every edge agrees with the oracle to the parity bar, for both edge
+    variants; without it the GPU and the oracle agree wherever the oracle's
+    interpolated states are physical."""
+    fdu = _fdu()
+    N = 12
+    m = make_mesh(N, L=float(N), periodic=True, jitter=0.0, diag="uniform")
+    a, b = 5 * N + 6, 6 * N + 6
+    rho = np.ones(m.nv)
+    rho[[a, b]] = 0.02
+    from paper_2102_12933_amd.inputs import primitive_to_conservative
+    w0 = primitive_to_conservative(rho, np.zeros(m.nv), np.zeros(m.nv), 0.8 * rho)
+    prep = fdu.Prep(m, deg=5, reorder=0)
+    A = prep.arrays()
+    o = Oracle(m, deg=5, positivity=True)
+    loc = np.searchsorted(o.edges, A["flux_edge"])
+    k = int(np.nonzero((o.sten6[:, 2] == a) & (o.sten6[:, 3] == b))[0][0])
+    ro = o.edge_fluxes(torch.from_numpy(w0)).numpy()
+    for ev in (0, 1):
+        s = fdu.Solver(prep, device=0, positivity=1)
+        s.set_variants(ev, 0)
+        w = torch.from_numpy(np.ascontiguousarray(w0[A["perm"]])).cuda()
+        r = s.edge_fluxes(w).cpu().numpy()
+        err = rel_err_per_component(r, ro[loc])
+        assert err.max() <= TOL, (ev, err)
+        row = int(np.nonzero(loc == k)[0][0])
+        np.testing.assert_allclose(r[row], ro[k], rtol=1e-13, atol=1e-15)
+    off = Oracle(m, deg=5, positivity=False)
+    wl, wr = off.edge_states(torch.from_numpy(w0))
+    ok = (off._physical(wl) & off._physical(wr)).numpy()
+    assert not ok[k] and ok.sum() > 0
+    s = fdu.Solver(prep, device=0, positivity=0)
+    r = s.edge_fluxes(torch.from_numpy(np.ascontiguousarray(w0[A["perm"]])).cuda()).cpu().numpy()
+    roff = off.edge_fluxes(torch.from_numpy(w0)).numpy()
+    good = ok[loc]
+    assert rel_err_per_component(r[good], roff[loc][good]).max() <= TOL
+
+
+def test_residual_leaves_the_state_unchanged(sod24_p5):
+    """fdu_residual and fdu_residual_vjp read w only: on a walled mesh the ghost
+    rows are filled in the library's own copy, so w's ghost rows may hold
+    anything and stay as they were; the result equals that of a filled state."""
+    c = sod24_p5
+    w = c.w_dev()
+    c.s.fill_ghosts(w)
+    R_ref = c.s.residual(w)
+    junk = w.clone()
+    junk[c.m.nv_real:] = 7.0
+    before = junk.clone()
+    R = c.s.residual(junk)
+    assert torch.equal(junk, before)
+    assert torch.equal(R, R_ref)
+    c.s.enable_adjoint()
+    Rbar = torch.from_numpy(np.random.default_rng(3).normal(size=(c.m.nv_real, 4))).cuda()
+    g_ref = c.s.residual_vjp(w, Rbar)
+    g = c.s.residual_vjp(junk, Rbar)
+    assert torch.equal(junk, before)
+    assert torch.equal(g, g_ref)

@@ -89,3 +89,22 @@ def test_rotated_sod_with_walls_on_the_regular_mesh():
     m2 = make_mesh(65, periodic=False, jitter=0.0, diag="uniform", ghost_layers=4, reflect_y=False)
     t2, _, ok2, _ = run_to(Oracle(m2, deg=5), sod_state(m2), 0.2, 0.5)
     assert not ok2, t2
+
+
+@pytest.mark.slow
+def test_rotated_sod_wall_corner_needs_a_smaller_cfl():
+    """On the regular 129 x 129 walled mesh one SSP-RK3 step at CFL 0.5 from the
+    Sod data leaves a non-physical state, first at the vertex where the interface
+    meets the reflecting wall y = 1 (the first stage's energy goes negative
+    there); at CFL 0.2 the run to t = 0.05 stays physical."""
+    m = make_mesh(129, periodic=False, jitter=0.0, diag="uniform", ghost_layers=4)
+    o = Oracle(m, deg=5)
+    w0 = torch.from_numpy(sod_state(m))
+    w1 = o.rk3_stage(0, w0, w0, o.cfl_dt(w0, 0.5))
+    rho, _, _, p = euler.primitives(w1[:m.nv_real])
+    i = int(torch.argmin(p))
+    assert float(p[i]) < 0
+    x, y = m.xy[i]
+    assert y == 1.0 and abs((x - 0.5) * np.cos(np.pi / 6) + (y - 0.5) * np.sin(np.pi / 6)) < 2 * m.h
+    t, n, ok, _ = run_to(o, sod_state(m), 0.05, 0.2)
+    assert ok and abs(t - 0.05) < 1e-12, (t, n)
