@@ -241,6 +241,21 @@ fdu_status fdu_rk_stage(fdu_solver* s, int k, const void* w_n, void* w_prev, voi
                         const double* dt_dev, void* stream);
 fdu_status fdu_rk_step(fdu_solver* s, void* w, void* scratch, double cfl, double* dt_dev, void* stream);
 
+/* fdu_rk_step_static: for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same step as fdu_rk_step (same kernels, same results bit for
+ * bit) with the two stage states in a static device array of the library
+ * instead of a caller workspace: w (device [nv_total][4], in/out), cfl and
+ * dt_dev as for fdu_rk_step.  Allocates nothing and calls no allocating
+ * routine.  The array holds 80 MiB (83,886,080 bytes) on every GPU the library
+ * runs on, until the process ends: two states of up to 1,310,720 vertices
+ * (nv_total) in FP64, 2,621,440 in FP32 storage; larger solvers get
+ * FDU_ERR_INVALID_ARG (use fdu_rk_step).  Every call on one GPU uses that GPU's
+ * array, so calls that overlap in time on one GPU (other streams, other
+ * threads) race; calls in stream order do not (each stage state is written
+ * before it is read within the call).  Errors as for fdu_rk_step. */
+fdu_status fdu_rk_step_static(fdu_solver* s, void* w, double cfl, double* dt_dev, void* stream);
+
 /* ------------------------------------------------------------------------
  * Adjoint (vector-Jacobian products) of the residual and of the SSP-RK3 stage
  * and step, for gradients through unrolled time stepping.

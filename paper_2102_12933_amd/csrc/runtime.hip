@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -51,6 +52,37 @@ struct DevBuf {
 }  // namespace fdu
 
 using namespace fdu;
+
+// Stage states of fdu_rk_step_static, for callers that cannot allocate: one
+// file-scope device array, which every GPU the library runs on holds (its own
+// copy) until the process ends.  Host code never uses the array's name as an
+// address: the device address of each GPU's copy is taken once per device with
+// hipGetSymbolAddress (fdu_create, with that device current) and kept in
+// g_static_scratch.
+constexpr size_t kStaticScratchBytes = size_t(80) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_scratch[kMaxDevices] = {};
+
+// With `device` current: records the device address of its copy of the array.
+void static_scratch_init(int device) {
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (device < 0 || device >= kMaxDevices) throw Error(FDU_ERR_UNSUPPORTED, "device index beyond 63");
+  if (g_static_scratch[device]) return;
+  void* p = nullptr;
+  FDU_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Error(FDU_ERR_HIP, "hipGetSymbolAddress returned no address for the static stage states");
+  g_static_scratch[device] = p;
+}
+
+void* static_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_static_scratch[device] : nullptr;
+}
+}  // namespace
 
 struct fdu_solver {
   int device = 0;
@@ -753,6 +785,13 @@ fdu_status fdu_create(fdu_solver** out, int hip_device, fdu_precision prec, cons
       delete s;
       throw Error(FDU_ERR_INVALID_ARG, "invalid scheme parameters");
     }
+    try {
+      DeviceGuard dg(hip_device);
+      static_scratch_init(hip_device);
+    } catch (...) {
+      delete s;
+      throw;
+    }
     *out = s;
   });
 }
@@ -1044,6 +1083,27 @@ fdu_status fdu_rk_step(fdu_solver* s, void* w, void* scratch, double cfl, double
       rk_step_t<double>(s, (double*)w, (double*)scratch, cfl, dt_dev, (hipStream_t)stream);
     else
       rk_step_t<float>(s, (float*)w, (float*)scratch, cfl, dt_dev, (hipStream_t)stream);
+  });
+}
+
+fdu_status fdu_rk_step_static(fdu_solver* s, void* w, double cfl, double* dt_dev, void* stream) {
+  return guard([&] {
+    ready(s);
+    need(w && dt_dev, "NULL argument");
+    const size_t elem = s->prec == FDU_F64 ? sizeof(double) : sizeof(float);
+    const size_t need_bytes = 2 * 4 * elem * (size_t)s->nv_total;
+    if (need_bytes > kStaticScratchBytes)
+      throw Error(FDU_ERR_INVALID_ARG, "fdu_rk_step_static: two stage states of " + std::to_string(s->nv_total) +
+                                           " vertices need " + std::to_string(need_bytes) +
+                                           " bytes, more than the static array's " +
+                                           std::to_string(kStaticScratchBytes) + " (use fdu_rk_step)");
+    void* st_buf = static_scratch(s->device);
+    if (!st_buf) throw Error(FDU_ERR_STATE, "static stage states not set up on this device");
+    DeviceGuard dg(s->device);
+    if (s->prec == FDU_F64)
+      rk_step_t<double>(s, (double*)w, (double*)st_buf, cfl, dt_dev, (hipStream_t)stream);
+    else
+      rk_step_t<float>(s, (float*)w, (float*)st_buf, cfl, dt_dev, (hipStream_t)stream);
   });
 }
 

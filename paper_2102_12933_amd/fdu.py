@@ -85,6 +85,7 @@ _SIGS = {
     "fdu_residual_vjp": (I32, [VP, VP, VP, VP, VP]),
     "fdu_rk_stage_vjp": (I32, [VP, I32, VP, VP, VP, VP, D, VP]),
     "fdu_rk_step_vjp": (I32, [VP, VP, VP, VP, VP, D, VP]),
+    "fdu_rk_step_static": (I32, [VP, VP, D, VP, VP]),
 }
 
 _lib = None
@@ -284,6 +285,11 @@ class Solver:
             raise ValueError("scratch must hold two states")
         _call("fdu_rk_step", self.handle, self._state(w), C.c_void_p(scratch.data_ptr()), float(cfl),
               self._dt(dt), _stream())
+
+    def rk_step_static(self, w, dt, cfl=0.0):
+        """fdu_rk_step without a workspace: the stage states live in the library's
+        static device array (no allocation; calls overlapping on one GPU race)."""
+        _call("fdu_rk_step_static", self.handle, self._state(w), float(cfl), self._dt(dt), _stream())
 
     # -- adjoint
     def enable_adjoint(self):
