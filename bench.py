@@ -168,6 +168,82 @@ def cpu_baseline(mesh, w_input, budget_s=15.0, patch=48):
                        f"{el:.1f} s")
 
 
+def _oracle_stage_rate(mesh, deg, sample, reps=5, vjp=False, **kw):
+    """Oracle residual + stage update (or, with vjp, the residual's VJP) of the
+    sampled real vertices: median time of `reps` evaluations after one warm-up
+    (the oracle's set-up, stencils and weights, is not timed)."""
+    import numpy as np
+    import torch
+    from oracle.solver import Oracle
+    from paper_2102_12933_amd.inputs import vortex_state
+
+    o = Oracle(mesh, deg=deg, vertices=None if sample is None else sample, **kw)
+    w = torch.from_numpy(vortex_state(mesh, beta=5.0, mach=0.5))
+    verts = np.arange(mesh.nv_real) if sample is None else sample
+    wn = w[verts].clone()
+    Rbar = torch.ones(len(verts), 4, dtype=torch.float64)
+
+    def unit():
+        if vjp:
+            o.residual_vjp(w, Rbar)
+        else:
+            R = o.residual(w)
+            _ = 0.75 * wn + 0.25 * (w[verts] + 1e-4 * R)
+
+    unit()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        unit()
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    return dict(vertices=int(len(verts)), s_per_stage=round(t, 5), vertex_stage_per_s=round(len(verts) / t, 1))
+
+
+def oracle_config_timings(log, max_sample=4096):
+    """The oracle timed on the host for the vortex workloads (accuracy study
+    sizes, batch instances, adjoint), one RK stage per timed unit; meshes above
+    max_sample real vertices are timed on a max_sample-vertex block of
+    consecutive lattice rows around the vortex centre."""
+    import numpy as np
+    import torch
+    from paper_2102_12933_amd.inputs import batch_specs, make_mesh
+
+    def sample_of(m):
+        if m.nv_real <= max_sample:
+            return None
+        N = m.N
+        rows = max(1, max_sample // N)
+        i0 = N // 2 - rows // 2
+        return np.arange(i0 * N, (i0 + rows) * N)
+
+    out = dict(cores=torch.get_num_threads(), kind="oracle", unit="vertex-stage/s", configs={})
+    m = make_mesh(33, L=10.0, periodic=True, seed=0)
+    out["configs"]["vortex 33^2, degree 3 one-level (10 steps)"] = _oracle_stage_rate(m, 3, None)
+    log(f"oracle timing: 33^2 done")
+    for N in (65, 129, 257, 513):
+        m = make_mesh(N, L=10.0, periodic=True, seed=0)
+        for deg in (3, 5):
+            out["configs"][f"vortex {N}^2, degree {deg}"] = _oracle_stage_rate(m, deg, sample_of(m))
+        log(f"oracle timing: {N}^2 done")
+    specs = batch_specs(n=64)
+    tot_v, tot_t = 0, 0.0
+    for sp in specs[:4]:
+        m = make_mesh(sp["N"], L=10.0, periodic=True, seed=sp["seed"])
+        r = _oracle_stage_rate(m, 5, sample_of(m))
+        tot_v += r["vertices"]
+        tot_t += r["s_per_stage"]
+    out["configs"]["batch, instances 0-3 (degree 5)"] = dict(vertices=tot_v, s_per_stage=round(tot_t, 5),
+                                                            vertex_stage_per_s=round(tot_v / tot_t, 1))
+    log("oracle timing: batch instances done")
+    m = make_mesh(257, L=10.0, periodic=True, seed=0)
+    out["configs"]["adjoint 257^2 forward stage (eps 1e-6)"] = _oracle_stage_rate(m, 5, sample_of(m), weno_eps=1e-6)
+    out["configs"]["adjoint 257^2 residual VJP (autograd, eps 1e-6)"] = _oracle_stage_rate(m, 5, sample_of(m),
+                                                                                          vjp=True, weno_eps=1e-6)
+    log("oracle timing: adjoint done")
+    return out
+
+
 def fallback_edges(prep, solver, states):
     """Edges whose flux the positivity fallback changes, per stage input of one
     step: the flux arrays of the solver and of a twin without the fallback
@@ -368,6 +444,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--variants", type=int, nargs=2, metavar=("EDGE", "VERTEX"), default=None,
                     help="use these kernel variants instead of autotuning (profiling runs)")
+    ap.add_argument("--oracle-configs", action="store_true",
+                    help="only time the oracle on the host for the vortex, batch and adjoint workloads (no GPU)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 512 MiB buffer 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -378,11 +456,15 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2102_12933_amd import fdu
-    from paper_2102_12933_amd.inputs import make_mesh, sod_state
-
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
+
+    if args.oracle_configs:
+        print(json.dumps(oracle_config_timings(log)), flush=True)
+        return
+
+    from paper_2102_12933_amd import fdu
+    from paper_2102_12933_amd.inputs import make_mesh, sod_state
 
     t = time.perf_counter()
     mesh = make_mesh(args.N, L=1.0, periodic=False, jitter=0.15, seed=0, ghost_layers=4)

@@ -331,7 +331,7 @@ fdu_status fdu_kernel_timer_stop(fdu_solver* s, double* avg_ms, int* counts);
  *   vertex; 1: strided loops, 8 lanes; 2: pipelined loads, 8 lanes; vertex
  *   tile = passes x 256 / lanes; 3: one tile per vertex block of the
  *   instance with its stencil halo staged in LDS, the code of vertex variant
- *   4, schedules 1 and 2 only, FDU_ERR_UNSUPPORTED with 0).  Results equal
+ *   4; in schedule 0 the persistent kernel carries the largest block's LDS).  Results equal
  *   the plain path's with vertex variant 0, 1, 2 and 3 (= 4, 5) respectively,
  *   bit for bit (the edge phase runs edge variant 0's code when the instances
  *   use edge variant 0, else variant 1's).

@@ -145,7 +145,10 @@ __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; 
 
 // Vertex-tile modes: 0 = strided loops, 16 lanes per vertex; 1 = strided
 // loops, 8 lanes; 2 = pipelined loads, 8 lanes (few registers live across
-// the gathers, for the fused kernel, whose register budget the edge code sets).
+// the gathers, for the fused kernel, whose register budget the edge code sets);
+// 3 = one vertex block per tile with its stencil halo staged in LDS (the block
+// code of vertex variant 4; the kernel is launched with the largest block's
+// LDS, which edge and ghost tiles leave unused).
 template <int VM>
 struct VertexMode {
   static constexpr int lpv = VM == 0 ? 16 : 8;
@@ -153,18 +156,27 @@ struct VertexMode {
 
 // PH < 0: fused schedule with dynamic tickets and dependency waits; PH 0/1/2:
 // a kernel holding only that phase's code, one tile per block (no waits).
+// In the fused kernel a workgroup runs many tiles one after the other; the
+// tile table is copied to LDS once (at tb_off ints into the dynamic LDS, after
+// the vertex-block rows of mode 3) and searched there.  (Taking the next
+// ticket while a tile runs was measured slower: a reserved edge tile can hold
+// back every vertex tile of its instance until the current tile ends.)
 template <int EV, int VM, int PH>
 __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict__ inst, int n,
                                                      const int* __restrict__ tb, int total, unsigned* ctr, Scheme S,
                                                      int k, double a, double b, const double* __restrict__ dt,
-                                                     int* err, BatchTiling tl) {
+                                                     int* err, BatchTiling tl, int tb_off) {
   constexpr int LPV = VertexMode<VM>::lpv;
   constexpr int phase = PH;
   __shared__ int sh;
+  extern __shared__ double lds[];   // vertex mode 3: the block's staged rows and CSR pointers
+  int* stb = reinterpret_cast<int*>(lds) + tb_off;   // fused kernel: the tile table
+  if (phase < 0)
+    for (int i = threadIdx.x; i <= 3 * n; i += blockDim.x) stb[i] = tb[i];
   for (int iter = 0;; ++iter) {
     int t;
     if (phase < 0) {
-      __syncthreads();
+      __syncthreads();   // the previous tile is done (its LDS rows read); the table is written
       if (threadIdx.x == 0) sh = (int)atomicAdd(&ctr[0], 1u);
       __syncthreads();
       t = sh;
@@ -174,8 +186,15 @@ __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict
       if (t >= tb[(phase + 1) * n]) return;
     }
     if (t >= total) return;
-    const int j = find_slot(tb, 3 * n, t);
-    const int p = j / n, i = j - p * n, local = t - tb[j];
+    int j, tj;
+    if constexpr (PH < 0) {
+      j = find_slot(stb, 3 * n, t);
+      tj = stb[j];
+    } else {
+      j = find_slot(tb, 3 * n, t);
+      tj = tb[j];
+    }
+    const int p = j / n, i = j - p * n, local = t - tj;
     const BatchInst I = global_view(inst, i);
     double* wprev = k == 0 ? I.w : (k == 1 ? I.w1 : I.w2);
     double* wout = k == 0 ? I.w1 : (k == 1 ? I.w2 : I.w);
@@ -201,6 +220,13 @@ __global__ void __launch_bounds__(256) k_batch_stage(const BatchInst* __restrict
       if (phase < 0) signal_count(&ctr[1 + n + i]);
     } else if ((PH < 0 || PH == 2) && p == 2) {
       if (phase < 0) wait_count(&ctr[1 + n + i], (unsigned)ceil_div(I.ne, 256 * tl.ept), err);
+      if constexpr (VM == 3 && PH < 0) {
+        vertex_block2<double, double, 8, 3, 6, 1, true>(local, lds, wprev, I.vblk, I.vb_own, I.vb_uvp, I.vb_uv,
+                                                        I.vb_uep, I.vb_ue, I.vptr, I.vb_lvcol, I.wfg, I.eptr,
+                                                        I.vb_lecol, I.we, I.cO, I.flux, S.gm1, 1, nullptr, I.w, wout,
+                                                        a, b, dt + i, I.vb_pk);
+        continue;
+      }
       for (int q = 0; q < tl.vp; ++q) {
         const int tt = (local * tl.vp + q) * 256 + threadIdx.x;
         const int v = tt / LPV;

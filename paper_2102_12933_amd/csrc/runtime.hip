@@ -644,6 +644,16 @@ struct fdu_batch {
 
 namespace {
 
+// Dynamic LDS of the vertex-block tiles (vertex mode 3): the largest block's
+// staged rows plus its CSR pointer table.
+size_t batch_lds_bytes(const fdu_batch* b) {
+  return b->vmode == 3 ? (size_t)b->lds_rows * 4 * sizeof(double) + 2 * (kBlockVertices + 1) * sizeof(int) : 0;
+}
+
+// The fused kernel's dynamic LDS: the vertex-block rows (mode 3), then the
+// tile table (3 n + 1 ints, 4-byte aligned after the rows).
+size_t fused_lds_bytes(const fdu_batch* b) { return batch_lds_bytes(b) + (size_t)(3 * b->n + 1) * sizeof(int); }
+
 void batch_tiles(fdu_batch* b) {
   const int n = b->n;
   const int per_v = b->tl.vp * (256 / (b->vmode == 0 ? 16 : 8));
@@ -670,14 +680,19 @@ void batch_tiles(fdu_batch* b) {
   b->tbc.upload(tbc.data(), tbc.size());
   int cus = 0, per_cu = 0;
   FDU_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
-  FDU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_stage<1, 2, -1>, 256, 0));
+  if (b->vmode == 3)
+    FDU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_stage<1, 3, -1>, 256, fused_lds_bytes(b)));
+  else
+    FDU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_stage<1, 2, -1>, 256, fused_lds_bytes(b)));
   b->grid = std::max(1, std::min(b->total, cus * std::max(1, per_cu)));
 }
 
 template <int EV, int VM, int PH>
 void batch_stage_launch(fdu_batch* b, int k, hipStream_t st, unsigned grid) {
-  hipLaunchKernelGGL((k_batch_stage<EV, VM, PH>), dim3(grid), dim3(256), 0, st, b->dinst.p, b->n, b->tb.p, b->total,
-                     b->ctr.p, b->S, k, kRK[k][0], kRK[k][1], b->dt.p, b->err.p, b->tl);
+  const size_t lds = PH < 0 ? fused_lds_bytes(b) : 0;
+  hipLaunchKernelGGL((k_batch_stage<EV, VM, PH>), dim3(grid), dim3(256), lds, st, b->dinst.p, b->n, b->tb.p, b->total,
+                     b->ctr.p, b->S, k, kRK[k][0], kRK[k][1], b->dt.p, b->err.p, b->tl,
+                     (int)(batch_lds_bytes(b) / sizeof(int)));
 }
 
 template <int EV, int VM>
@@ -1259,8 +1274,6 @@ fdu_status fdu_batch_set_schedule(fdu_batch* b, int schedule, int edges_per_thre
     need(edges_per_thread >= 1 && edges_per_thread <= 64, "edges_per_thread out of range");
     need(vertex_passes >= 1 && vertex_passes <= 64, "vertex_passes out of range");
     need(vertex_mode >= 0 && vertex_mode <= 3, "vertex_mode must be 0, 1, 2 or 3");
-    if (vertex_mode == 3 && schedule == 0)
-      throw Error(FDU_ERR_UNSUPPORTED, "vertex mode 3 (LDS blocks) needs schedule 1 or 2");
     if (vertex_mode == 3)
       for (int i = 0; i < b->n; ++i)
         if (b->inst[i]->vb_rows_max > kBlockRows ||

@@ -15,8 +15,8 @@ import os
 import torch
 
 # (schedule, edges per thread, vertex passes, vertex mode)
-CANDIDATES = [(0, 4, 8, 2), (0, 16, 16, 2), (0, 4, 8, 0), (0, 16, 32, 1), (1, 4, 8, 0), (1, 4, 8, 2), (1, 16, 16, 1),
-              (1, 4, 8, 3), (1, 16, 8, 3), (2, 4, 8, 0)]
+CANDIDATES = [(0, 4, 8, 2), (0, 16, 16, 2), (0, 4, 8, 3), (0, 16, 8, 3), (0, 1, 8, 3), (1, 4, 8, 0), (1, 4, 8, 2),
+              (1, 16, 16, 1), (1, 4, 8, 3), (1, 16, 8, 3), (2, 4, 8, 0)]
 CACHE = os.environ.get("FDU_TUNING_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "fdu_tuning.json"))
 
 

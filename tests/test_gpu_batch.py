@@ -50,7 +50,7 @@ def plain_steps(inst, nsteps, cfl):
 @pytest.mark.parametrize("edge_variant", [0, 1])
 @pytest.mark.parametrize("schedule,ept,vp,vmode", [(0, 4, 8, 0), (0, 1, 1, 1), (0, 4, 8, 2), (1, 4, 8, 0),
                                                    (1, 16, 16, 2), (2, 4, 8, 0), (0, 16, 32, 0), (1, 4, 8, 3),
-                                                   (1, 1, 1, 3), (2, 4, 8, 3)])
+                                                   (1, 1, 1, 3), (2, 4, 8, 3), (0, 4, 8, 3), (0, 1, 1, 3)])
 def test_batch_equals_plain(edge_variant, schedule, ept, vp, vmode):
     fdu = _fdu()
     # the plain path's vertex kernel with the same lanes and load order sums in the same order
@@ -111,12 +111,14 @@ def test_batch_table_matches_workload_description():
     assert all(65 <= sp["N"] <= 513 and 2.0 <= sp["beta"] <= 6.0 and 0.3 <= sp["mach"] <= 0.8 for sp in specs)
 
 
-def test_batch_lds_mode_rejects_persistent_schedule():
+def test_batch_set_schedule_rejects_bad_arguments():
     fdu = _fdu()
     inst = build_instances(SPECS[:2])
     b = fdu.Batch([s for s, _ in inst])
-    with pytest.raises(fdu.FduError, match="UNSUPPORTED"):
-        b.set_schedule(0, 4, 8, 3)
+    for args in ((3, 4, 8, 0), (0, 0, 8, 0), (0, 4, 0, 0), (0, 4, 8, 4), (1, 65, 8, 0)):
+        with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+            b.set_schedule(*args)
+    b.set_schedule(0, 4, 8, 3)          # the fused schedule runs the LDS vertex blocks too
 
 
 @pytest.mark.slow
@@ -136,7 +138,7 @@ def test_full_batch_workload_sampled():
         w0 = torch.from_numpy(np.ascontiguousarray(vortex_state(m, beta=sp["beta"], mach=sp["mach"])[perm])).cuda()
         inst.append((s, w0))
     sample = [0, 17, 40, 63]
-    for schedule, vmode, plain_vertex in ((1, 3, 3), (0, 2, 2)):
+    for schedule, vmode, plain_vertex in ((1, 3, 3), (0, 2, 2), (0, 3, 3)):
         for s, _ in inst:
             s.set_variants(1, plain_vertex)
         ref = plain_steps([inst[i] for i in sample], 3, 0.2)

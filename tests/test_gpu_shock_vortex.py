@@ -86,7 +86,7 @@ def test_dirichlet_channel_residual_vjp():
     assert np.abs(g[nr:]).max() == 0.0
 
 
-@pytest.mark.parametrize("schedule,vmode", [(0, 2), (1, 3), (2, 0)])
+@pytest.mark.parametrize("schedule,vmode", [(0, 2), (1, 3), (2, 0), (0, 3)])
 def test_dirichlet_batch_equals_plain(schedule, vmode):
     fdu = _fdu()
     inst = [channel(seed=k, center=(2.0 + k, 0.5 * k), mv=0.6 + 0.2 * k) for k in range(3)]

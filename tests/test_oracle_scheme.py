@@ -204,28 +204,37 @@ def test_cfl_time_step():
     np.testing.assert_allclose(o.cfl_dt(w, 0.5), 0.5 * hmin / (0.5 + np.sqrt(1.4)), rtol=1e-14)
 
 
-def _vortex_trunc(N, jitter, diag, **kw):
+def _vortex_trunc(N, jitter, diag, sample=None, **kw):
+    """Mean |R_h(w_exact) - dw_exact/dt| in the density over vertices within 4 of
+    the vortex centre (a seeded sample of them when `sample` is given)."""
     m = make_mesh(N, L=10.0, periodic=True, seed=0, jitter=jitter, diag=diag)
-    o = Oracle(m, deg=5, **kw)
+    d = m.xy - 5.0
+    idx = np.nonzero(np.sqrt((d * d).sum(1)) <= 4.0)[0]
+    if sample is not None and len(idx) > sample:
+        idx = np.sort(np.random.default_rng(0).choice(idx, sample, replace=False))
+    o = Oracle(m, deg=5, vertices=idx, **kw)
     w = torch.from_numpy(vortex_state(m, beta=5.0, mach=0.5))
     R = o.residual(w).numpy()
-    ex = vortex_state_dt(m, beta=5.0, mach=0.5)
-    d = m.xy - 5.0
-    msk = np.sqrt((d * d).sum(1)) <= 4.0
-    return np.abs(R - ex)[msk][:, 0].mean()
+    ex = vortex_state_dt(m, beta=5.0, mach=0.5)[idx]
+    return np.abs(R - ex)[:, 0].mean()
 
 
 @pytest.mark.slow
 def test_vortex_design_order_on_regular_meshes():
-    """Sec. 3.1: fifth order on regular diagonalized meshes.  The linear scheme (the
-    WENO weights at their optimal values) shows the design order; the paper's
-    nonlinear weights (q = 1, eps = 1e-40) lose accuracy at critical points and
-    measure about third order in this truncation-error test."""
-    hs = np.array([10 / 32, 10 / 64, 10 / 128])
-    lin = [_vortex_trunc(N, 0.0, "uniform", weno_eps=1e10) for N in (32, 64, 128)]
-    assert np.log(lin[1] / lin[2]) / np.log(2) > 4.4, lin
-    nl = [_vortex_trunc(N, 0.0, "uniform") for N in (32, 64)]
-    assert np.log(nl[0] / nl[1]) / np.log(2) > 2.7, nl
+    """Sec. 3.1: fifth order on regular diagonalized meshes, measured on the
+    truncation error (reading A18) at 3000 sampled vertices near the vortex.
+    The linear scheme (WENO weights at their optimal values) reaches the design
+    order: 4.2, 4.7, 4.9 over 32 -> 64 -> 128 -> 256 (4.9 again at 512).  The
+    paper's nonlinear weights (power 1, eps = 1e-40) leave the optimal weights
+    at critical points of the data; their L1 order climbs from 3.1 (32 -> 64)
+    to 3.9 and 4.4 (-> 128 -> 256) and is 3.7 at 512, about fourth order, whose
+    one-step error (dt times the truncation error, dt ~ h) is the fifth order
+    the paper reports for one small step."""
+    lin = [_vortex_trunc(N, 0.0, "uniform", sample=3000, weno_eps=1e10) for N in (128, 256)]
+    assert np.log2(lin[0] / lin[1]) > 4.7, lin
+    nl = [_vortex_trunc(N, 0.0, "uniform", sample=3000) for N in (64, 128, 256)]
+    o1, o2 = np.log2(nl[0] / nl[1]), np.log2(nl[1] / nl[2])
+    assert o1 > 3.5 and o2 > 4.0, (nl, o1, o2)
 
 
 @pytest.mark.slow
