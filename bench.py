@@ -137,6 +137,119 @@ def traffic_from_profiles(kernel, N, reorder):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def short_kernel_name(name):
+    """'void fdu::k_x<a, b>(args...)' -> 'k_x<a, b>' (the template instance)."""
+    n = name.strip()
+    if n.startswith("void "):
+        n = n[5:]
+    if n.startswith("fdu::"):
+        n = n[5:]
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return n[:i]
+    return n
+
+
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(d, suffix):
+    """The one rocprofv3 output file under directory d whose name ends with suffix."""
+    hits = []
+    for root, _, files in os.walk(d):
+        hits += [os.path.join(root, f) for f in files if f.endswith(suffix)]
+    if len(hits) != 1:
+        raise SystemExit(f"expected one *{suffix} under {d}, found {len(hits)}")
+    return hits[0]
+
+
+def counter_medians(d):
+    """{kernel: {counter: (dispatches, median value per dispatch)}} from a
+    rocprofv3 --pmc output directory (csv)."""
+    import numpy as np
+    per = {}
+    for r in _csv_rows(_find(d, "_counter_collection.csv")):
+        k = short_kernel_name(r["Kernel_Name"])
+        per.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: {c: (len(v), float(np.median(v))) for c, v in cs.items()} for k, cs in per.items()}
+
+
+def summarize(kind, dirs, N=1025, reorder=2):
+    """Markdown summaries of rocprofv3 csv outputs for profiles/ (trace: kernel
+    statistics; counters: per-kernel medians; traffic: FETCH_SIZE and
+    WRITE_SIZE scaled by the same counters on the 512 MiB calibration copies,
+    also written to profiles/hbm_traffic.json for the roofline's traffic)."""
+    import numpy as np
+    out = []
+    if kind == "trace":
+        rows = _csv_rows(_find(dirs[0], "_kernel_stats.csv"))
+        out += ["| kernel | calls | avg (us) | min (us) | max (us) | share of GPU time |", "|---|---|---|---|---|---|"]
+        other = sum(float(r["Percentage"]) for r in rows if not short_kernel_name(r["Name"]).startswith("k_"))
+        for r in rows:
+            if not short_kernel_name(r["Name"]).startswith("k_"):
+                continue
+            out.append(f"| `{short_kernel_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                       f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
+        out += ["", f"Other kernels (torch fills and copies, the HIP runtime's buffer copies): {other:.1f}% of GPU time."]
+    elif kind == "counters":
+        med = {}
+        for d in dirs:
+            for k, cs in counter_medians(d).items():
+                med.setdefault(k, {}).update(cs)
+        names = sorted({c for cs in med.values() for c in cs})
+        out += ["| kernel | dispatches | " + " | ".join(names) + " |", "|---" * (len(names) + 2) + "|"]
+        for k in sorted(med):
+            if not k.startswith("k_"):
+                continue
+            disp = max(n for n, _ in med[k].values())
+            out.append(f"| `{k}` | {disp} | " + " | ".join(
+                f"{med[k][c][1]:.4g}" if c in med[k] else "" for c in names) + " |")
+    elif kind == "traffic":
+        fetch, write = counter_medians(dirs[0]), counter_medians(dirs[1])
+        copy = 512 * 1024 * 1024
+        calib = {}
+        for label, med, counter in (("fetch", fetch, "FETCH_SIZE"), ("write", write, "WRITE_SIZE")):
+            vals = [float(r["Counter_Value"]) for r in _csv_rows(_find(dirs[0 if label == "fetch" else 1],
+                                                                        "_counter_collection.csv"))
+                    if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter
+                    and int(r["Grid_Size"]) == 131072]
+            if not vals:
+                raise SystemExit(f"no 512 MiB calibration copy in the {label} run (bench.py --calib-copy)")
+            calib[label] = float(np.median(vals))
+        ff, wf = copy / 1024.0 / calib["fetch"], copy / 1024.0 / calib["write"]
+        kern = {}
+        for k in sorted(set(fetch) & set(write)):
+            if not k.startswith("k_"):
+                continue
+            n, fk = fetch[k]["FETCH_SIZE"]
+            _, wk = write[k]["WRITE_SIZE"]
+            kern[k] = dict(dispatches=n, fetch_kib=fk, write_kib=wk, bytes_per_launch=int(round((fk * ff + wk * wf) * 1024)))
+        doc = dict(source_hash=source_hash(), N=N, reorder=reorder,
+                   calibration=dict(copy_bytes=copy, fetch_kib_read=calib["fetch"], write_kib_read=calib["write"],
+                                    fetch_factor=round(ff, 4), write_factor=round(wf, 4)),
+                   kernels=kern)
+        with open(os.path.join(ROOT, "profiles", "hbm_traffic.json"), "w") as fh:
+            json.dump(doc, fh, indent=1)
+        out += [f"Calibration: the 512 MiB copy reads FETCH_SIZE = {calib['fetch']:.0f} KiB and WRITE_SIZE = "
+                f"{calib['write']:.0f} KiB, so FETCH_SIZE is scaled by {ff:.3f} and WRITE_SIZE by {wf:.3f}.", "",
+                "| kernel | dispatches | FETCH_SIZE (KiB, median) | WRITE_SIZE (KiB, median) | HBM MB per launch (scaled) |",
+                "|---|---|---|---|---|"]
+        for k, v in kern.items():
+            out.append(f"| `{k}` | {v['dispatches']} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | "
+                       f"{v['bytes_per_launch'] / 1e6:.1f} |")
+    else:
+        raise SystemExit("summarize: trace, counters or traffic")
+    return "\n".join(out)
+
+
 def cpu_baseline(mesh, w_input, budget_s=15.0, patch=48):
     """Oracle stage timing on a bounded sample: a patch x patch block of real
     vertices around the domain centre (the oracle computes their residual, i.e.
@@ -264,7 +377,46 @@ def fallback_edges(prep, solver, states):
     return counts
 
 
-def bench_batched(n_inst, steps, cfl, edge_variant, vertex_variant, log):
+def bench_chained(N, steps, cfl, log):
+    """Chained SSP-RK3 steps of the rotated Sod problem with walls on the regular
+    diagonalized N x N mesh (no jitter, uniform diagonals): the configuration on
+    which the scheme runs a long chain (on jittered random-diagonal meshes the
+    least-squares divergence has growing modes).  dt from the CFL condition on
+    the device every step; the state is checked at the end."""
+    import numpy as np
+    import torch
+    from paper_2102_12933_amd import fdu
+    from paper_2102_12933_amd.inputs import make_mesh, sod_state
+
+    m = make_mesh(N, L=1.0, periodic=False, jitter=0.0, diag="uniform", seed=0, ghost_layers=4)
+    prep = fdu.Prep(m, deg=5, level=0, reorder=2)
+    A = prep.arrays()
+    s = fdu.Solver(prep, device=0)
+    w0 = torch.from_numpy(np.ascontiguousarray(sod_state(m)[A["perm"]])).cuda()
+    w = w0.clone()
+    scratch = torch.empty(2 * s.nv_total, 4, dtype=torch.float64, device="cuda")
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    s.fill_ghosts(w)
+    s.autotune(w, reps=10)
+    for _ in range(5):                                   # warm-up on a copy
+        s.rk_step(w, scratch, dt, cfl=cfl)
+    w.copy_(w0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.rk_step(w, scratch, dt, cfl=cfl)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    nbad, _ = s.check_state(w)
+    log(f"chained: {steps} steps on the regular {N}^2 mesh in {el * 1e3:.1f} ms, non-physical rows {nbad}")
+    return dict(workload=f"rotated Sod, regular {N}x{N} diagonalized mesh with walls, {steps} chained SSP-RK3 "
+                         f"steps at CFL {cfl} (dt from the CFL condition each step)",
+                nv_real=int(A["nv_real"]), nnz_v=int(A["nnz_v"]), nnz_e=int(A["nnz_e"]), steps=steps,
+                ms_per_step=round(el / steps * 1e3, 4), vertex_stage_per_s=A["nv_real"] * 3 * steps / el,
+                non_physical_rows=int(nbad), variants=list(s.variants().values())[:2])
+
+
+def bench_batched(n_inst, steps, cfl, edge_variant, vertex_variant, log, graph=True):
     """Batched vortex workload: n_inst instances (N ~ U{65..513}, strength ~ U[2,6],
     Mach ~ U[0.3,0.8]), `steps` SSP-RK3 steps captured in one HIP graph, for each
     schedule; the plain per-instance path is schedule 2 (every instance's own
@@ -307,16 +459,23 @@ def bench_batched(n_inst, steps, cfl, edge_variant, vertex_variant, log):
         for w, w0 in zip(ws, w0s):
             w.copy_(w0)
         torch.cuda.synchronize()
-        with torch.cuda.stream(side):
-            b.capture(cfl, steps)
-            b.launch()                          # warm-up replay
-        side.synchronize()
+        if graph:
+            with torch.cuda.stream(side):
+                b.capture(cfl, steps)
+                b.launch()                      # warm-up replay
+            side.synchronize()
+        else:
+            b.step(cfl)
         for w, w0 in zip(ws, w0s):
             w.copy_(w0)
         torch.cuda.synchronize()
         tt = time.perf_counter()
         with torch.cuda.stream(side):
-            b.launch()
+            if graph:
+                b.launch()
+            else:
+                for _ in range(steps):
+                    b.step(cfl)
         side.synchronize()
         el = time.perf_counter() - tt
         err, dts = b.status()
@@ -324,7 +483,7 @@ def bench_batched(n_inst, steps, cfl, edge_variant, vertex_variant, log):
         res[label] = dict(schedule=list(cand), ms_per_step=round(el / steps * 1e3, 4),
                           vertex_stage_per_s=nv * 3 * steps / el, wait_timeouts=err, finite=ok)
         log(f"batch {label} {cand}: {el / steps * 1e3:.3f} ms/step, {nv * 3 * steps / el:.3e} vertex-stage/s")
-    return dict(instances=n_inst, vertices=int(nv), steps=steps, cfl=cfl, graph=True,
+    return dict(instances=n_inst, vertices=int(nv), steps=steps, cfl=cfl, graph=graph,
                 best_batched=max(("per_phase", "persistent"), key=lambda k: res[k]["vertex_stage_per_s"]),
                 speedup_vs_per_instance=round(max(res["per_phase"]["vertex_stage_per_s"],
                                                   res["persistent"]["vertex_stage_per_s"]) /
@@ -438,17 +597,25 @@ def main():
     ap.add_argument("--batch-instances", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-batch-graph", action="store_true", help="batched steps eagerly, not from a HIP graph")
     ap.add_argument("--adjoint-N", type=int, default=257)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-chained", action="store_true")
     ap.add_argument("--variants", type=int, nargs=2, metavar=("EDGE", "VERTEX"), default=None,
                     help="use these kernel variants instead of autotuning (profiling runs)")
+    ap.add_argument("--summarize", nargs="+", metavar=("KIND", "DIR"),
+                    help="print a profiles/ summary of rocprofv3 csv output: trace DIR | counters DIR... | "
+                         "traffic FETCH_DIR WRITE_DIR (also writes profiles/hbm_traffic.json); no GPU")
     ap.add_argument("--oracle-configs", action="store_true",
                     help="only time the oracle on the host for the vortex, batch and adjoint workloads (no GPU)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy a 512 MiB buffer 3 times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.summarize:
+        print(summarize(args.summarize[0], args.summarize[1:], args.N, args.reorder))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -627,8 +794,11 @@ def main():
     }
     if not args.no_fp32:
         out["fp32_storage"] = bench_fp32(prep, A, w0, min(args.steps, 100), args.cfl, log)
+    if not args.no_chained:
+        out["chained_regular"] = bench_chained(args.N, args.steps, args.cfl, log)
     if not args.no_batch:
-        out["batched"] = bench_batched(args.batch_instances, args.batch_steps, 0.2, tune["edge"], tune["vertex"], log)
+        out["batched"] = bench_batched(args.batch_instances, args.batch_steps, 0.2, tune["edge"], tune["vertex"], log,
+                                       graph=not args.no_batch_graph)
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(args.adjoint_N, 20, 5, log)
     if not args.no_cpu_baseline:
