@@ -123,9 +123,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel, N, reorder):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
+def traffic_from_profiles(kernel, N, reorder, grid):
+    """HBM bytes per launch of `kernel` at grid size `grid` (threads) from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    sources; else None."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
@@ -133,7 +134,7 @@ def traffic_from_profiles(kernel, N, reorder):
         d = json.load(fh)
     if d.get("source_hash") != source_hash() or d.get("N") != N or d.get("reorder") != reorder:
         return None
-    k = d.get("kernels", {}).get(kernel)
+    k = d.get("kernels", {}).get(kernel, {}).get(str(grid))
     return None if k is None else k.get("bytes_per_launch")
 
 
@@ -172,12 +173,13 @@ def _find(d, suffix):
 
 
 def counter_medians(d):
-    """{kernel: {counter: (dispatches, median value per dispatch)}} from a
-    rocprofv3 --pmc output directory (csv)."""
+    """{(kernel, grid size): {counter: (dispatches, median value per dispatch)}}
+    from a rocprofv3 --pmc output directory (csv): the same kernel runs on
+    several workloads, told apart by their grid sizes."""
     import numpy as np
     per = {}
     for r in _csv_rows(_find(d, "_counter_collection.csv")):
-        k = short_kernel_name(r["Kernel_Name"])
+        k = (short_kernel_name(r["Kernel_Name"]), int(r["Grid_Size"]))
         per.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     return {k: {c: (len(v), float(np.median(v))) for c, v in cs.items()} for k, cs in per.items()}
 
@@ -190,48 +192,59 @@ def summarize(kind, dirs, N=1025, reorder=2):
     import numpy as np
     out = []
     if kind == "trace":
-        rows = _csv_rows(_find(dirs[0], "_kernel_stats.csv"))
-        out += ["| kernel | calls | avg (us) | min (us) | max (us) | share of GPU time |", "|---|---|---|---|---|---|"]
-        other = sum(float(r["Percentage"]) for r in rows if not short_kernel_name(r["Name"]).startswith("k_"))
+        # one row per (kernel, grid size): the same kernel runs on several workloads
+        rows = _csv_rows(_find(dirs[0], "_kernel_trace.csv"))
+        groups, total = {}, 0.0
         for r in rows:
-            if not short_kernel_name(r["Name"]).startswith("k_"):
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            total += d
+            key = (short_kernel_name(r["Kernel_Name"]), int(r["Grid_Size_X"]))
+            groups.setdefault(key, []).append(d)
+        out += ["| kernel | grid (threads) | calls | avg (us) | median (us) | min (us) | max (us) | share of GPU time |",
+                "|---|---|---|---|---|---|---|---|"]
+        rest = 0.0
+        for (k, g), ds in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+            share = 100.0 * sum(ds) / total
+            if not k.startswith("k_") or share < 0.1:
+                rest += share
                 continue
-            out.append(f"| `{short_kernel_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
-                       f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
-        out += ["", f"Other kernels (torch fills and copies, the HIP runtime's buffer copies): {other:.1f}% of GPU time."]
+            out.append(f"| `{k}` | {g} | {len(ds)} | {np.mean(ds):.1f} | {np.median(ds):.1f} | {min(ds):.1f} | "
+                       f"{max(ds):.1f} | {share:.1f}% |")
+        out += ["", f"Launches below 0.1% of GPU time each and non-library kernels (torch fills and copies, the HIP "
+                    f"runtime's buffer copies): {rest:.1f}% of GPU time together."]
     elif kind == "counters":
         med = {}
         for d in dirs:
             for k, cs in counter_medians(d).items():
                 med.setdefault(k, {}).update(cs)
         names = sorted({c for cs in med.values() for c in cs})
-        out += ["| kernel | dispatches | " + " | ".join(names) + " |", "|---" * (len(names) + 2) + "|"]
+        out += ["| kernel | grid (threads) | dispatches | " + " | ".join(names) + " |", "|---" * (len(names) + 3) + "|"]
         for k in sorted(med):
-            if not k.startswith("k_"):
+            if not k[0].startswith("k_"):
                 continue
             disp = max(n for n, _ in med[k].values())
-            out.append(f"| `{k}` | {disp} | " + " | ".join(
+            out.append(f"| `{k[0]}` | {k[1]} | {disp} | " + " | ".join(
                 f"{med[k][c][1]:.4g}" if c in med[k] else "" for c in names) + " |")
     elif kind == "traffic":
         fetch, write = counter_medians(dirs[0]), counter_medians(dirs[1])
         copy = 512 * 1024 * 1024
         calib = {}
-        for label, med, counter in (("fetch", fetch, "FETCH_SIZE"), ("write", write, "WRITE_SIZE")):
-            vals = [float(r["Counter_Value"]) for r in _csv_rows(_find(dirs[0 if label == "fetch" else 1],
-                                                                        "_counter_collection.csv"))
-                    if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter
-                    and int(r["Grid_Size"]) == 131072]
-            if not vals:
-                raise SystemExit(f"no 512 MiB calibration copy in the {label} run (bench.py --calib-copy)")
-            calib[label] = float(np.median(vals))
+        for label, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+            # the calibration copies are the run's last three dispatches (bench.py --calib-copy)
+            rows = _csv_rows(_find(dirs[0 if label == "fetch" else 1], "_counter_collection.csv"))
+            rows = sorted((r for r in rows if r["Counter_Name"] == counter), key=lambda r: int(r["Dispatch_Id"]))[-3:]
+            if len(rows) < 3 or not all("copyBuffer" in r["Kernel_Name"] for r in rows):
+                raise SystemExit(f"the {label} run does not end with the calibration copies (bench.py --calib-copy)")
+            calib[label] = float(np.median([float(r["Counter_Value"]) for r in rows]))
         ff, wf = copy / 1024.0 / calib["fetch"], copy / 1024.0 / calib["write"]
         kern = {}
         for k in sorted(set(fetch) & set(write)):
-            if not k.startswith("k_"):
+            if not k[0].startswith("k_"):
                 continue
             n, fk = fetch[k]["FETCH_SIZE"]
             _, wk = write[k]["WRITE_SIZE"]
-            kern[k] = dict(dispatches=n, fetch_kib=fk, write_kib=wk, bytes_per_launch=int(round((fk * ff + wk * wf) * 1024)))
+            kern.setdefault(k[0], {})[str(k[1])] = dict(dispatches=n, fetch_kib=fk, write_kib=wk,
+                                                        bytes_per_launch=int(round((fk * ff + wk * wf) * 1024)))
         doc = dict(source_hash=source_hash(), N=N, reorder=reorder,
                    calibration=dict(copy_bytes=copy, fetch_kib_read=calib["fetch"], write_kib_read=calib["write"],
                                     fetch_factor=round(ff, 4), write_factor=round(wf, 4)),
@@ -240,11 +253,12 @@ def summarize(kind, dirs, N=1025, reorder=2):
             json.dump(doc, fh, indent=1)
         out += [f"Calibration: the 512 MiB copy reads FETCH_SIZE = {calib['fetch']:.0f} KiB and WRITE_SIZE = "
                 f"{calib['write']:.0f} KiB, so FETCH_SIZE is scaled by {ff:.3f} and WRITE_SIZE by {wf:.3f}.", "",
-                "| kernel | dispatches | FETCH_SIZE (KiB, median) | WRITE_SIZE (KiB, median) | HBM MB per launch (scaled) |",
-                "|---|---|---|---|---|"]
-        for k, v in kern.items():
-            out.append(f"| `{k}` | {v['dispatches']} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | "
-                       f"{v['bytes_per_launch'] / 1e6:.1f} |")
+                "| kernel | grid (threads) | dispatches | FETCH_SIZE (KiB, median) | WRITE_SIZE (KiB, median) | "
+                "HBM MB per launch (scaled) |", "|---|---|---|---|---|---|"]
+        for k, per_grid in kern.items():
+            for g, v in per_grid.items():
+                out.append(f"| `{k}` | {g} | {v['dispatches']} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | "
+                           f"{v['bytes_per_launch'] / 1e6:.1f} |")
     else:
         raise SystemExit("summarize: trace, counters or traffic")
     return "\n".join(out)
@@ -734,7 +748,10 @@ def main():
         ms = kt[k]
         kern[k] = dict(avg_ms=ms, launches=kcount[k], bytes=nb[k], gbs=nb[k] / (ms * 1e-3) / 1e9)
     names = dict(edge=EDGE_KERNELS[tune["edge"]], vertex=VERTEX_KERNELS[tune["vertex"]])
-    traffic = traffic_from_profiles(names[dom], args.N, args.reorder)
+    grids = dict(edge=-(-A["ne_flux"] // 256) * 256,
+                 vertex=(blocks["n_blocks"] * 256 if blocks is not None
+                         else -(-A["nv_real"] * {0: 16, 1: 8, 2: 8}.get(tune["vertex"], 8) // 256) * 256))
+    traffic = traffic_from_profiles(names[dom], args.N, args.reorder, grids[dom])
     alg_bytes = per_unit[dom] * A["nv_real"]
     achieved = alg_bytes / (kt[dom] * 1e-3) / 1e9
     # context for the roof: what a plain 1 GiB device-to-device copy reaches on this GPU

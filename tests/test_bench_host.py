@@ -76,11 +76,14 @@ def test_traffic_lookup_follows_the_source_hash(tmp_path, monkeypatch):
     with open(path) as fh:
         d = json.load(fh)
     kernel = next(iter(d["kernels"]))
+    grid = next(iter(d["kernels"][kernel]))
     if d["source_hash"] == bench.source_hash():
-        assert bench.traffic_from_profiles(kernel, d["N"], d["reorder"]) == d["kernels"][kernel]["bytes_per_launch"]
-    # another workload size or vertex order never borrows the measurement
-    assert bench.traffic_from_profiles(kernel, d["N"] + 1, d["reorder"]) is None
-    assert bench.traffic_from_profiles(kernel, d["N"], (d["reorder"] + 1) % 3) is None
+        assert (bench.traffic_from_profiles(kernel, d["N"], d["reorder"], int(grid))
+                == d["kernels"][kernel][grid]["bytes_per_launch"])
+    # another workload size, vertex order or grid never borrows the measurement
+    assert bench.traffic_from_profiles(kernel, d["N"] + 1, d["reorder"], int(grid)) is None
+    assert bench.traffic_from_profiles(kernel, d["N"], (d["reorder"] + 1) % 3, int(grid)) is None
+    assert bench.traffic_from_profiles(kernel, d["N"], d["reorder"], int(grid) + 256) is None
     # a summary taken on other sources is ignored
     fake_root = tmp_path
     (fake_root / "profiles").mkdir()
@@ -88,5 +91,10 @@ def test_traffic_lookup_follows_the_source_hash(tmp_path, monkeypatch):
     (fake_root / "profiles" / "hbm_traffic.json").write_text(json.dumps(d2))
     monkeypatch.setattr(bench, "ROOT", str(fake_root))
     monkeypatch.setattr(bench, "source_hash", lambda: "f" * 16)
-    assert bench.traffic_from_profiles(kernel, d["N"], d["reorder"]) is None
+    assert bench.traffic_from_profiles(kernel, d["N"], d["reorder"], int(grid)) is None
 
+
+def test_kernel_names_shorten_to_template_instances():
+    assert bench.short_kernel_name("void fdu::k_edge_flux_lean<double, double>(double const*, int const*, "
+                                   "double const*, double*, int, fdu::Scheme)") == "k_edge_flux_lean<double, double>"
+    assert bench.short_kernel_name("fdu::k_cfl_final(double const*, int, double, double*)") == "k_cfl_final"
