@@ -756,7 +756,7 @@ def main():
     achieved = alg_bytes / (kt[dom] * 1e-3) / 1e9
     # context for the roof: what a plain 1 GiB device-to-device copy reaches on this GPU
     # (skipped in counter-calibration runs, whose only large copies must be the 512 MiB ones)
-    copy_gbs = None
+    copy_gbs = read_gbs = None
     if not args.calib_copy:
         src = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -768,7 +768,15 @@ def main():
         e1.record()
         e1.synchronize()
         copy_gbs = round(2 * src.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
-        del src, dst
+        # and a read-only stream over the same 1 GiB (torch's sum): the vertex step is 97% reads
+        acc = src.sum()
+        e0.record()
+        for _ in range(5):
+            acc = src.sum()
+        e1.record()
+        e1.synchronize()
+        read_gbs = round(src.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+        del src, dst, acc
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=names[dom], variant=tune[dom], avg_ms=round(kt[dom], 5), launches=kcount[dom],
@@ -778,7 +786,8 @@ def main():
                     stored_frac=round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4),
                     timing=f"timing-only HIP events around every {dom} launch in the timed region",
                     other_kernel_timing=f"{other}: the same events in a separate run of {n_other} of the same steps",
-                    copy_gbs=copy_gbs)
+                    copy_gbs=copy_gbs, read_gbs=read_gbs,
+                    traffic_gbs=(round(traffic / (kt[dom] * 1e-3) / 1e9, 1) if traffic else None))
     nv_real = A["nv_real"]
     value = nv_real * 3 * args.steps / el
     out = {

@@ -126,6 +126,10 @@ def test_prep_rejects_bad_input():
         fdu.Prep(m2, deg=3)
     with pytest.raises(fdu.FduError, match="INVALID_ARG"):
         fdu.Prep(m, deg=9)
+    empty = type(m)(**{**m.__dict__, "xy": np.zeros((0, 2)), "nv_real": 0, "tri": np.zeros((0, 3), np.int32),
+                       "edges": np.zeros((0, 2), np.int32)})
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        fdu.Prep(empty, deg=3)
 
 
 def test_degree_six_needs_more_than_a_mirrored_wall_stencil():

@@ -119,6 +119,8 @@ def test_batch_set_schedule_rejects_bad_arguments():
         with pytest.raises(fdu.FduError, match="INVALID_ARG"):
             b.set_schedule(*args)
     b.set_schedule(0, 4, 8, 3)          # the fused schedule runs the LDS vertex blocks too
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        fdu.Batch([])                   # an empty batch
 
 
 @pytest.mark.slow

@@ -295,6 +295,41 @@ def test_full_size_sod_sampled(sod1025_prep, edge, vertex):
     assert err1.max() <= 1e-14
 
 
+@pytest.mark.slow
+def test_largest_mesh_sampled():
+    """A 2049^2 rotated Sod mesh, four times the benchmark's (4.2 M real
+    vertices, 12.7 M flux edges, about 35 k vertex blocks): one SSP-RK3 step
+    with the default kernels, then the residual of the stepped state at
+    sampled vertices (near the interface, at random, walls, corners) against
+    the oracle."""
+    fdu = _fdu()
+    N = 2049
+    m = make_mesh(N, L=1.0, periodic=False, seed=0, ghost_layers=4)
+    prep = fdu.Prep(m, deg=5, reorder=2)
+    perm = prep.arrays()["perm"]
+    s = fdu.Solver(prep, device=0)
+    w = torch.from_numpy(np.ascontiguousarray(sod_state(m)[perm])).cuda()
+    scratch = torch.empty(2 * s.nv_total, 4, dtype=torch.float64, device="cuda")
+    dt = torch.empty(1, dtype=torch.float64, device="cuda")
+    s.rk_step(w, scratch, dt, cfl=0.2)
+    R = s.residual(w).cpu().numpy()
+    w_in = np.empty((m.nv, 4))
+    w_in[perm] = w.cpu().numpy()
+    iperm = np.argsort(perm)
+    rng = np.random.default_rng(5)
+    a = np.deg2rad(30.0)
+    xy = m.xy[:m.nv_real]
+    sd = (xy[:, 0] - 0.5) * np.cos(a) + (xy[:, 1] - 0.5) * np.sin(a)
+    near = np.nonzero(np.abs(sd) < 0.005)[0]
+    wall = np.nonzero((xy[:, 1] < 1e-12) | (xy[:, 1] > 1 - 1e-12))[0]
+    sample = np.unique(np.concatenate([rng.choice(near, 200, replace=False), rng.choice(m.nv_real, 100, replace=False),
+                                       rng.choice(wall, 40, replace=False), [0, N - 1, N * (N - 1), m.nv_real - 1]]))
+    Ro = Oracle(m, deg=5, vertices=sample).residual(torch.from_numpy(w_in)).numpy()
+    err = rel_err_per_component(R[iperm[sample]], Ro)
+    print(f"{N}^2 sampled residual rel err", err, "sample", len(sample))
+    assert err.max() <= TOL
+
+
 @pytest.mark.parametrize("edge,vertex", [(e, v) for e in range(2) for v in range(6)])
 def test_kernel_variants(vortex33_p5, sod24_p5, edge, vertex):
     """Every kernel variant computes the same residual (to the parity bar)."""
