@@ -200,3 +200,51 @@ def test_unrolled_gradient_small_vs_oracle():
 def test_unrolled_gradient_257():
     """Adjoint workload at 257^2 (66,049 vertices): 20 steps, checkpoints every 5."""
     _unrolled_grad_check(257, 20, 5, oracle_check=False)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("workload", ["vortex257", "sod1025"])
+def test_residual_vjp_sampled_at_full_size(workload):
+    """The residual VJP at the workloads' full sizes, in the bench's launch
+    shape (Hilbert order, default kernels): a cotangent supported on a sample
+    of vertices (near the Sod interface, walls, corners, at random) makes
+    (dR/dw)^T Rbar depend only on the residual at the sample, which the
+    oracle computes there and differentiates by autograd; the GPU's whole
+    output field (every row) is compared with it.  The adjoint workload (257^2
+    jittered periodic vortex) and the headline mesh (1025^2 walled rotated Sod
+    with a smooth perturbation, where the positivity fallback and the mirror
+    ghosts enter the VJP)."""
+    fdu = _fdu()
+    if workload == "vortex257":
+        m = make_mesh(257, L=10.0, periodic=True, seed=0)
+        w0 = vortex_state(m, beta=5.0, mach=0.5)
+        rng = np.random.default_rng(11)
+        sample = np.unique(rng.choice(m.nv_real, 300, replace=False))
+    else:
+        m = make_mesh(1025, L=1.0, periodic=False, seed=0, ghost_layers=4)
+        w0 = perturbed_sod(m)
+        rng = np.random.default_rng(12)
+        a = np.deg2rad(30.0)
+        xy = m.xy[:m.nv_real]
+        sd = (xy[:, 0] - 0.5) * np.cos(a) + (xy[:, 1] - 0.5) * np.sin(a)
+        near = np.nonzero(np.abs(sd) < 0.01)[0]
+        wall = np.nonzero((xy[:, 1] < 1e-12) | (xy[:, 1] > 1 - 1e-12) | (xy[:, 0] < 1e-12) | (xy[:, 0] > 1 - 1e-12))[0]
+        sample = np.unique(np.concatenate([rng.choice(near, 150, replace=False), rng.choice(m.nv_real, 100, replace=False),
+                                           rng.choice(wall, 60, replace=False), [0, 1024, 1025 * 1024, m.nv_real - 1]]))
+    prep = fdu.Prep(m, deg=5, reorder=2)
+    perm = prep.arrays()["perm"]
+    s = fdu.Solver(prep, device=0, weno_eps=ADJ_EPS)
+    s.enable_adjoint()
+    Rbar = np.zeros((m.nv, 4))
+    Rbar[sample] = rng.normal(size=(len(sample), 4))
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a[perm])).cuda()
+
+    wb = s.residual_vjp(dev(w0), dev(Rbar)[:m.nv_real].contiguous()).cpu().numpy()
+    o = Oracle(m, deg=5, vertices=sample, weno_eps=ADJ_EPS)
+    ref = o.residual_vjp(torch.from_numpy(w0), torch.from_numpy(Rbar[sample])).numpy()
+    err = rel_err_per_component(wb, ref[perm])
+    print(workload, "sampled residual VJP rel err", err, "sample", len(sample),
+          "rows touched", int(np.count_nonzero(np.abs(ref).sum(1))))
+    assert err.max() <= TOL
