@@ -276,6 +276,13 @@ fdu_status fdu_rk_step_static(fdu_solver* s, void* w, double cfl, double* dt_dev
  *   recomputed forward stages and for the reverse sweep): recomputes the stage
  *   states from w_n (in/out: ghost rows filled) and writes
  *   wbar_n := (dw_{n+1}/dw_n)^T wbar_np1.  scratch: device, 4 states.
+ * fdu_rk_step_vjp_stages: the same adjoint given the step's stage states
+ *   w_1, w_2 (the two states fdu_rk_step leaves in its workspace, in that
+ *   order, or fdu_rk_stage's outputs for k = 0, 1) instead of recomputing them:
+ *   for checkpointed unrolling, whose segment recompute already produces
+ *   them.  w_n, w_1, w_2 are in/out (ghost rows filled); scratch: device, 2
+ *   states.  Equal to fdu_rk_step_vjp bit for bit when the stage states are
+ *   the ones it would recompute.
  * Errors: FDU_ERR_STATE if the adjoint is not enabled; FDU_ERR_INVALID_ARG for
  * NULL or aliased arguments.  Asynchronous on stream; no allocation.
  */
@@ -283,6 +290,8 @@ fdu_status fdu_enable_adjoint(fdu_solver* s);
 fdu_status fdu_residual_vjp(fdu_solver* s, const void* w, const void* Rbar, void* wbar, void* stream);
 fdu_status fdu_rk_stage_vjp(fdu_solver* s, int k, void* w_prev, const void* obar, void* wbar_n, void* wbar_prev,
                             double dt, void* stream);
+fdu_status fdu_rk_step_vjp_stages(fdu_solver* s, void* w_n, void* w_1, void* w_2, const void* wbar_np1,
+                                  void* wbar_n, void* scratch, double dt, void* stream);
 fdu_status fdu_rk_step_vjp(fdu_solver* s, void* w_n, const void* wbar_np1, void* wbar_n, void* scratch, double dt,
                            void* stream);
 

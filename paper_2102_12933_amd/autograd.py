@@ -2,9 +2,11 @@
 
 ResidualFn   R = residual(w); backward calls fdu_residual_vjp.
 RKUnroll     w_N = N SSP-RK3 steps at a fixed dt from w_0; the forward keeps a
-             state every ``ckpt_every`` steps, the backward recomputes the states
-             of each segment from its checkpoint and applies fdu_rk_step_vjp
-             (which itself recomputes the stage states) in reverse.
+             state every ``ckpt_every`` steps, the backward recomputes each
+             segment from its checkpoint stage by stage, keeping every step's
+             stage states, and applies fdu_rk_step_vjp_stages in reverse (the
+             stage states are recomputed once, not again inside each step's
+             adjoint).
 
 Every forward and backward pass runs in the HIP library; these classes only
 hold tensors and order the calls.
@@ -53,20 +55,28 @@ class RKUnroll(torch.autograd.Function):
         dev = wbar.device
         dt_dev = torch.full((1,), dt, dtype=torch.float64, device=dev)
         scratch2 = torch.empty(2 * solver.nv_total, 4, dtype=wbar.dtype, device=dev)
-        scratch4 = torch.empty(4 * solver.nv_total, 4, dtype=wbar.dtype, device=dev)
         g = wbar.contiguous().clone()
         g[solver.nv_real:] = 0.0
         gn = torch.empty_like(g)
         for seg in reversed(range(len(ckpts))):
             start = seg * every
             stop = min(start + every, nsteps)
-            states = [ckpts[seg].clone()]
-            w = ckpts[seg].clone()
-            for _ in range(start, stop - 1):
-                solver.rk_step(w, scratch2, dt_dev)
-                states.append(w.clone())
+            # recompute the segment stage by stage, keeping every step's stage
+            # states (the step adjoints then need no forward recompute of
+            # their own; the last step needs only its first two stages)
+            saved = []
+            wn = ckpts[seg].clone()
+            for i in range(start, stop):
+                w1, w2 = torch.empty_like(wn), torch.empty_like(wn)
+                solver.rk_stage(0, wn, wn, w1, dt_dev)
+                solver.rk_stage(1, wn, w1, w2, dt_dev)
+                saved.append((wn, w1, w2))
+                if i + 1 < stop:
+                    wnext = torch.empty_like(wn)
+                    solver.rk_stage(2, wn, w2, wnext, dt_dev)
+                    wn = wnext
             for j in reversed(range(stop - start)):
-                solver.rk_step_vjp(states[j], g, gn, scratch4, dt)
+                solver.rk_step_vjp_stages(*saved[j], g, gn, scratch2, dt)
                 g, gn = gn, g
         return g, None, None, None, None
 

@@ -586,21 +586,11 @@ void rk_stage_vjp_t(fdu_solver* s, int k, T* wprev, const T* obar, T* wbar_n, T*
   }
 }
 
-// Adjoint of one SSP-RK3 step at a fixed dt: recompute the stage states from
-// w_n with the same dt (written to the device once, so the recomputed forward
-// stages and the reverse sweep cannot use different values), then run the
-// stages backwards.  scratch holds 4 states.
+// The stages of one SSP-RK3 step run backwards, given the step's stage
+// states w_n, w1, w2 (ghost rows filled here); g2, g1: two work states.
 template <class T>
-void rk_step_vjp_t(fdu_solver* s, T* wn, const T* wbar_np1, T* wbar_n, T* scratch, double dt, hipStream_t st) {
-  const size_t S4 = 4 * (size_t)s->nv_total;
-  T* w1 = scratch;
-  T* w2 = scratch + S4;
-  T* g2 = scratch + 2 * S4;
-  T* g1 = scratch + 3 * S4;
-  hipLaunchKernelGGL(k_set_value, dim3(1), dim3(64), 0, st, s->dt_adj.p, dt);
-  launch_check();
-  rk_stage_t<T>(s, 0, wn, wn, w1, s->dt_adj.p, st);
-  rk_stage_t<T>(s, 1, wn, w1, w2, s->dt_adj.p, st);
+void rk_step_vjp_rev_t(fdu_solver* s, T* wn, T* w1, T* w2, const T* wbar_np1, T* wbar_n, T* g2, T* g1, double dt,
+                       hipStream_t st) {
   // wbar_n := 0 on every row; the 1/3 wbar_np1 term of the last stage is
   // added by that stage's adjoint (its a_2 axpy)
   hipLaunchKernelGGL(k_scale<T>, dim3(nblocks(s->nv_total)), dim3(256), 0, st, wbar_n, 0.0, wbar_np1,
@@ -611,6 +601,22 @@ void rk_step_vjp_t(fdu_solver* s, T* wn, const T* wbar_np1, T* wbar_n, T* scratc
   rk_stage_vjp_t<T>(s, 0, wn, g1, wbar_n, g2, dt, st);
   hipLaunchKernelGGL(k_axpy_real<T>, dim3(nblocks(s->nv_real)), dim3(256), 0, st, wbar_n, 1.0, g2, (int)s->nv_real);
   launch_check();
+}
+
+// Adjoint of one SSP-RK3 step at a fixed dt: recompute the stage states from
+// w_n with the same dt (written to the device once, so the recomputed forward
+// stages and the reverse sweep cannot use different values), then run the
+// stages backwards.  scratch holds 4 states.
+template <class T>
+void rk_step_vjp_t(fdu_solver* s, T* wn, const T* wbar_np1, T* wbar_n, T* scratch, double dt, hipStream_t st) {
+  const size_t S4 = 4 * (size_t)s->nv_total;
+  T* w1 = scratch;
+  T* w2 = scratch + S4;
+  hipLaunchKernelGGL(k_set_value, dim3(1), dim3(64), 0, st, s->dt_adj.p, dt);
+  launch_check();
+  rk_stage_t<T>(s, 0, wn, wn, w1, s->dt_adj.p, st);
+  rk_stage_t<T>(s, 1, wn, w1, w2, s->dt_adj.p, st);
+  rk_step_vjp_rev_t<T>(s, wn, w1, w2, wbar_np1, wbar_n, scratch + 2 * S4, scratch + 3 * S4, dt, st);
 }
 
 }  // namespace
@@ -1178,6 +1184,29 @@ fdu_status fdu_rk_step_vjp(fdu_solver* s, void* w_n, const void* wbar_np1, void*
     else
       rk_step_vjp_t<float>(s, (float*)w_n, (const float*)wbar_np1, (float*)wbar_n, (float*)scratch, dt,
                            (hipStream_t)stream);
+  });
+}
+
+fdu_status fdu_rk_step_vjp_stages(fdu_solver* s, void* w_n, void* w_1, void* w_2, const void* wbar_np1,
+                                  void* wbar_n, void* scratch, double dt, void* stream) {
+  return guard([&] {
+    ready_adjoint(s);
+    need(w_n && w_1 && w_2 && wbar_np1 && wbar_n && scratch, "NULL argument");
+    need(wbar_n != wbar_np1, "wbar_n must not alias wbar_np1");
+    need(w_n != w_1 && w_n != w_2 && w_1 != w_2, "the stage states must be distinct");
+    need(wbar_n != w_n && wbar_n != w_1 && wbar_n != w_2, "wbar_n must not alias a stage state");
+    need(std::isfinite(dt), "dt must be finite");
+    DeviceGuard dg(s->device);
+    const size_t S4 = 4 * (size_t)s->nv_total;
+    if (s->prec == FDU_F64) {
+      double* g = (double*)scratch;
+      rk_step_vjp_rev_t<double>(s, (double*)w_n, (double*)w_1, (double*)w_2, (const double*)wbar_np1,
+                                (double*)wbar_n, g, g + S4, dt, (hipStream_t)stream);
+    } else {
+      float* g = (float*)scratch;
+      rk_step_vjp_rev_t<float>(s, (float*)w_n, (float*)w_1, (float*)w_2, (const float*)wbar_np1, (float*)wbar_n, g,
+                               g + S4, dt, (hipStream_t)stream);
+    }
   });
 }
 

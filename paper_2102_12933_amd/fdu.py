@@ -85,6 +85,7 @@ _SIGS = {
     "fdu_residual_vjp": (I32, [VP, VP, VP, VP, VP]),
     "fdu_rk_stage_vjp": (I32, [VP, I32, VP, VP, VP, VP, D, VP]),
     "fdu_rk_step_vjp": (I32, [VP, VP, VP, VP, VP, D, VP]),
+    "fdu_rk_step_vjp_stages": (I32, [VP, VP, VP, VP, VP, VP, VP, D, VP]),
     "fdu_rk_step_static": (I32, [VP, VP, D, VP, VP]),
 }
 
@@ -313,6 +314,14 @@ class Solver:
             raise ValueError("scratch must hold four states")
         _call("fdu_rk_step_vjp", self.handle, self._state(w_n), self._state(wbar_np1), self._state(wbar_n),
               C.c_void_p(scratch.data_ptr()), float(dt), _stream())
+
+    def rk_step_vjp_stages(self, w_n, w_1, w_2, wbar_np1, wbar_n, scratch, dt: float):
+        """fdu_rk_step_vjp with the step's stage states given (not recomputed)."""
+        if not (scratch.is_cuda and scratch.dtype == self.dtype and scratch.is_contiguous()
+                and scratch.numel() >= 8 * self.nv_total):
+            raise ValueError("scratch must hold two states")
+        _call("fdu_rk_step_vjp_stages", self.handle, self._state(w_n), self._state(w_1), self._state(w_2),
+              self._state(wbar_np1), self._state(wbar_n), C.c_void_p(scratch.data_ptr()), float(dt), _stream())
 
     # -- kernel variants
     def set_variants(self, edge: int, vertex: int):

@@ -248,3 +248,30 @@ def test_residual_vjp_sampled_at_full_size(workload):
     print(workload, "sampled residual VJP rel err", err, "sample", len(sample),
           "rows touched", int(np.count_nonzero(np.abs(ref).sum(1))))
     assert err.max() <= TOL
+
+
+@pytest.mark.parametrize("N,per,G,deg,state", [(16, True, 0, 5, "vortex"), (14, False, 4, 5, "sod")])
+def test_step_vjp_with_given_stages_equals_step_vjp(N, per, G, deg, state):
+    """fdu_rk_step_vjp_stages, given the stage states of the forward stages at
+    the same dt, equals fdu_rk_step_vjp (which recomputes them) bit for bit;
+    aliased stage states are refused."""
+    fdu = _fdu()
+    c = AdjCase(N, per, G, deg, state)
+    dt = 0.5 * c.o.cfl_dt(torch.from_numpy(c.w0), 0.3)
+    rng = np.random.default_rng(3)
+    ybar = c.dev(np.concatenate([rng.normal(size=(c.m.nv_real, 4)), np.zeros((c.m.ng, 4))]))
+    wn = c.dev(c.w0)
+    out1 = torch.empty_like(wn)
+    c.s.rk_step_vjp(wn.clone(), ybar, out1, torch.empty(4 * c.m.nv, 4, dtype=torch.float64, device="cuda"), dt)
+    dt_dev = torch.full((1,), dt, dtype=torch.float64, device="cuda")
+    w0, w1, w2 = wn.clone(), torch.empty_like(wn), torch.empty_like(wn)
+    c.s.rk_stage(0, w0, w0, w1, dt_dev)
+    c.s.rk_stage(1, w0, w1, w2, dt_dev)
+    out2 = torch.empty_like(wn)
+    scratch2 = torch.empty(2 * c.m.nv, 4, dtype=torch.float64, device="cuda")
+    c.s.rk_step_vjp_stages(w0, w1, w2, ybar, out2, scratch2, dt)
+    assert torch.equal(out1, out2)
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        c.s.rk_step_vjp_stages(w0, w1, w1, ybar, out2, scratch2, dt)
+    with pytest.raises(fdu.FduError, match="INVALID_ARG"):
+        c.s.rk_step_vjp_stages(w0, w1, w2, ybar, w1, scratch2, dt)
